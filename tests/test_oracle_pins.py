@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a naive DFT,
+a dense LU solve, a closed-form eigenvector solution, the paper's Table 3
+values, conservation/invariance properties, or finite differences.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+T = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64)  # noqa: E731
+
+
+def make_box(nx, ny, nz, gamma=2.0, lx=2 * np.pi, lz=np.pi):
+    return O.Box(nx, ny, nz, lx, lz, synth.tanh_faces(ny, gamma))
+
+
+# ---------------------------------------------------------------- grid (Table 3)
+def test_tanh_mapping_reproduces_table3():
+    rows = [l.split() for l in open(os.path.join(HERE, "golden", "table3_wall_spacing.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for name, ret, ny, dmin, dmax, g in rows:
+        d = np.diff(synth.tanh_faces(int(ny), float(g))) * float(ret)
+        # the table prints 2-3 significant figures
+        assert abs(d.min() - float(dmin)) <= 0.0051 + 0.02 * float(dmin), name
+        assert abs(d.max() - float(dmax)) / float(dmax) < 0.01, name
+
+
+# ---------------------------------------------------------------- transforms
+@pytest.mark.parametrize("nx,nz", [(12, 6), (16, 24), (8, 18), (6, 4)])
+def test_forward_transform_is_the_dft(nx, nz):
+    ny = 3
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((ny, nz, nx))
+    fh = O.forward_transform(T(f)).numpy()
+    i = np.arange(nx)
+    k = np.arange(nz)
+    kx = np.arange(nx // 2 + 1)
+    # exact integer reduction of the phase before the trig call
+    ex = np.exp(-2j * np.pi * ((kx[:, None] * i[None, :]) % nx) / nx)   # (nkx, nx)
+    ez = np.exp(-2j * np.pi * ((k[:, None] * k[None, :]) % nz) / nz)    # (nz, nz)
+    naive = np.einsum("jzi,ai,bz->jba", f, ex, ez)
+    assert np.abs(fh - naive).max() < 1e-12 * np.abs(naive).max()
+    back = O.inverse_transform(T(0) + torch.tensor(naive), nx).numpy()
+    assert np.abs(back - f).max() < 1e-13
+
+
+# ---------------------------------------------------------------- Thomas
+def test_thomas_matches_dense_lu():
+    rng = np.random.default_rng(1)
+    n, L = 37, 5
+    a = rng.uniform(0.5, 2, n)
+    c = rng.uniform(0.5, 2, n)
+    b = -(a + c)[:, None] - rng.uniform(0.0, 3.0, (n, L))
+    d = rng.standard_normal((n, L)) + 1j * rng.standard_normal((n, L))
+    x = O.thomas(T(a)[:, None], T(b), T(c)[:, None], torch.tensor(d)).numpy()
+    for l in range(L):
+        A = np.diag(b[:, l]) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        ref = np.linalg.solve(A, d[:, l])
+        assert np.abs(x[:, l] - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- closed form
+@pytest.mark.parametrize("m,n,l", [(1, 0, 0), (0, 2, 0), (3, 1, 2), (0, 0, 3),
+                                   (8, 3, 5), (2, 6, 1), (0, 1, 7)])
+def test_uniform_grid_closed_form(m, n, l):
+    """Uniform y: cos(pi l (j+1/2)/ny) is an eigenvector of the Neumann
+    3-point operator with eigenvalue -(2 sin(pi l/(2 ny))/dy)^2 (DCT-II), so
+    the discrete solution is f divided by the total eigenvalue."""
+    nx, ny, nz = 16, 12, 12
+    box = O.Box(nx, ny, nz, 2 * np.pi, np.pi, synth.uniform_faces(ny))
+    i = np.arange(nx)[None, None, :]
+    k = np.arange(nz)[None, :, None]
+    j = np.arange(ny)[:, None, None]
+    phi, psi = 0.3, -1.1
+    f = (np.cos(2 * np.pi * m * i / nx + phi) * np.cos(2 * np.pi * n * k / nz + psi)
+         * np.cos(np.pi * l * (j + 0.5) / ny))
+    dx, dz, dy = 2 * np.pi / nx, np.pi / nz, 2.0 / ny
+    lam = -((2 * np.sin(np.pi * m / nx) / dx) ** 2 + (2 * np.sin(np.pi * n / nz) / dz) ** 2
+            + (2 * np.sin(np.pi * l / (2 * ny)) / dy) ** 2)
+    p = O.poisson(T(f), box).numpy()
+    assert np.abs(p - f / lam).max() < 1e-13 * np.abs(f / lam).max()
+
+
+# ---------------------------------------------------------------- brute force
+def _dense_laplacian(box):
+    """L_h assembled entry by entry from the staggered 7-point stencil."""
+    nx, ny, nz = box.nx, box.ny, box.nz
+    N = nx * ny * nz
+    A = np.zeros((N, N))
+    idx = lambda j, k, i: (j * nz + (k % nz)) * nx + (i % nx)  # noqa: E731
+    yf = box.y_faces
+    yc = 0.5 * (yf[1:] + yf[:-1])
+    for j in range(ny):
+        h = yf[j + 1] - yf[j]
+        for k in range(nz):
+            for i in range(nx):
+                r = idx(j, k, i)
+                for di in (-1, 1):
+                    A[r, idx(j, k, i + di)] += 1 / box.dx ** 2
+                    A[r, r] -= 1 / box.dx ** 2
+                for dk in (-1, 1):
+                    A[r, idx(j, k + dk, i)] += 1 / box.dz ** 2
+                    A[r, r] -= 1 / box.dz ** 2
+                if j + 1 < ny:       # flux through the upper face
+                    g = 1 / ((yc[j + 1] - yc[j]) * h)
+                    A[r, idx(j + 1, k, i)] += g
+                    A[r, r] -= g
+                if j > 0:            # flux through the lower face
+                    g = 1 / ((yc[j] - yc[j - 1]) * h)
+                    A[r, idx(j - 1, k, i)] += g
+                    A[r, r] -= g
+    return A
+
+
+def test_bruteforce_dense_8cubed():
+    nx = ny = nz = 8
+    box = make_box(nx, ny, nz, gamma=2.0)
+    A = _dense_laplacian(box)
+    wts = np.repeat(np.diff(box.y_faces), nz * nx)
+    f = synth.uniform_rhs(nx, ny, nz, seed=3).reshape(-1)
+    fc = f - (wts @ f) / wts.sum()
+    N = A.shape[0]
+    B = np.zeros((N + 1, N + 1))
+    B[:N, :N] = A
+    B[:N, N] = wts
+    B[N, :N] = wts
+    sol = np.linalg.solve(B, np.concatenate([fc, [0.0]]))
+    ref = sol[:N]
+    p = O.poisson(T(f.reshape(ny, nz, nx)), box).numpy().reshape(-1)
+    assert abs(sol[N]) < 1e-10
+    assert np.abs(p - ref).max() < 1e-11 * np.abs(ref).max()
+    # and the oracle's operator is the same matrix
+    Lp = O.laplacian_p(torch.tensor(ref.reshape(ny, nz, nx)), box).numpy().reshape(-1)
+    assert np.abs(Lp - A @ ref).max() < 1e-10 * np.abs(A @ ref).max()
+
+
+def test_stretched_operator_converges_to_second_derivative():
+    """On a smooth stretched grid the y part of L_h tends to d2/dy2 for a
+    Neumann-compatible profile: errors shrink under refinement."""
+    errs = []
+    for ny in (32, 64, 128):
+        box = make_box(4, ny, 4, gamma=1.5)
+        yc = 0.5 * (box.y_faces[1:] + box.y_faces[:-1])
+        prof = np.cos(np.pi * (yc + 1.0))
+        p = np.broadcast_to(prof[:, None, None], (ny, 4, 4)).copy()
+        Lp = O.laplacian_p(T(p), box).numpy()[:, 0, 0]
+        exact = -np.pi ** 2 * prof
+        errs.append(np.abs(Lp - exact).max())
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1]
+
+
+def test_manufactured_solution_and_gauge():
+    box = make_box(16, 24, 12, gamma=2.5)
+    rng = np.random.default_rng(7)
+    ps = T(rng.standard_normal((24, 12, 16)))
+    ps = ps - O.mean_w(ps, box)
+    f = O.laplacian_p(ps, box)
+    p = O.poisson(f, box)
+    assert (p - ps).abs().max() < 1e-11 * ps.abs().max()
+    assert abs(O.mean_w(p, box).item()) < 1e-15
+    # a constant added to f changes nothing (compatibility projection)
+    p2 = O.poisson(f + 3.7, box)
+    assert (p2 - p).abs().max() < 1e-11 * p.abs().max()
+
+
+# ---------------------------------------------------------------- PDD
+def _lines(box, L=None):
+    a, c, k2 = O.line_coefficients(box)
+    k2 = k2.reshape(-1)
+    if L is not None:
+        k2 = k2[1:L + 1]
+    b = -(a + c)[:, None] - k2[None, :]
+    return a, b, c, k2
+
+
+def test_pdd_one_and_two_partitions_equal_thomas():
+    box = make_box(16, 64, 16, gamma=2.0)
+    a, b, c, k2 = _lines(box, L=40)
+    rng = np.random.default_rng(2)
+    d = torch.tensor(rng.standard_normal((64, 40)) + 1j * rng.standard_normal((64, 40)))
+    ref = O.thomas(a[:, None], b, c[:, None], d)
+    x1 = O.pdd_solve(a, b, c, d, 1, drop=True)
+    assert torch.equal(x1, ref)
+    x2 = O.pdd_solve(a, b, c, d, 2, drop=True)   # p = 2: nothing to drop
+    assert (x2 - ref).abs().max() < 1e-12 * ref.abs().max()
+
+
+@pytest.mark.parametrize("p", [4, 8, 16])
+def test_pdd_exact_reduced_system_equals_thomas(p):
+    box = make_box(16, 64, 16, gamma=2.5)
+    a, b, c, k2 = _lines(box, L=60)
+    rng = np.random.default_rng(p)
+    d = torch.tensor(rng.standard_normal((64, 60)) + 1j * rng.standard_normal((64, 60)))
+    ref = O.thomas(a[:, None], b, c[:, None], d)
+    x = O.pdd_solve(a, b, c, d, p, drop=False)
+    err = ((x - ref).abs().max(0).values / ref.abs().max(0).values).max()
+    assert err < 1e-11
+
+
+def test_pdd_drop_error_bounded_by_indicator():
+    """The drop discards the corner terms; its error scales with their size
+    delta (largest at low wavenumbers, negligible at high ones)."""
+    box = make_box(64, 64, 64, gamma=2.0)
+    a, c, k2 = O.line_coefficients(box)
+    k2 = k2.reshape(-1)
+    order = torch.argsort(k2)
+    sel = torch.cat([order[1:20], order[-20:]])
+    b = -(a + c)[:, None] - k2[sel][None, :]
+    rng = np.random.default_rng(11)
+    d = torch.tensor(rng.standard_normal((64, 39)) + 1j * rng.standard_normal((64, 39)))
+    ref = O.thomas(a[:, None], b, c[:, None], d)
+    x = O.pdd_solve(a, b, c, d, 4, drop=True)
+    delta = O.pdd_indicator(a, b, c, 4)
+    err = (x - ref).abs().max(0).values / ref.abs().max(0).values
+    assert (err <= 50 * delta + 1e-13).all()
+    assert err[:19].max() > 1e-6          # low modes: drop is not valid
+    assert err[19:].max() < 1e-13         # high modes: drop exact to round-off
+    assert (delta[19:] < 1e-12).all()
+
+
+# ---------------------------------------------------------------- projection
+def test_projection_invariants():
+    box = make_box(16, 16, 12, gamma=2.5)
+    u, v, w = (T(x) for x in synth.uniform_velocity(16, 16, 12, seed=4))
+
+    def P(a, b, c):
+        p = O.poisson(O.divergence(a, b, c, box), box)
+        g = O.gradient(p, box)
+        return a - g[0], b - g[1], c - g[2]
+
+    pu = P(u, v, w)
+    d = O.divergence(*pu, box)
+    assert d.abs().max() < 1e-13 * O.divergence(u, v, w, box).abs().max()
+    ppu = P(*pu)
+    assert max((x - y).abs().max() for x, y in zip(pu, ppu)) < 1e-12
+    # self-adjoint in the face-volume inner product
+    a2 = tuple(T(x) for x in synth.uniform_velocity(16, 16, 12, seed=9))
+    wf_c = (box.dx * box.dz * box.dy)[:, None, None]
+    wf_v = torch.cat([box.dx * box.dz * box.dyc, torch.zeros(1, dtype=torch.float64)])[:, None, None]
+    W = (wf_c, wf_v, wf_c)
+
+    def ip(x, y):
+        return sum((xi * yi * wi).sum() for xi, yi, wi in zip(x, y, W))
+    vv = (u, v, w)  # the seeded v already has a zero top-wall plane
+    pa2 = P(*a2)
+    lhs, rhs = ip(pu, a2), ip(vv, pa2)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+def test_projection_step_runs_divergence_free():
+    box = make_box(16, 16, 12, gamma=2.0)
+    u, v, w = (T(x) for x in synth.perturbed_poiseuille(16, 16, 12, box.y_faces, seed=0))
+    u1, v1, w1, p = O.projection_step(u, v, w, box, 1e-3, 1 / 550, 3 / 550, return_pressure=True)
+    assert O.divergence(u1, v1, w1, box).abs().max() < 1e-10
+    assert (v1[-1] == 0).all()
+    assert abs(O.mean_w(p, box).item()) < 1e-14
+
+
+# ---------------------------------------------------------------- momentum RHS
+def test_advection_galilean_and_conservation():
+    box = make_box(12, 10, 8, gamma=2.0)
+    ny, nz, nx = 10, 8, 12
+    z = torch.zeros(ny, nz, nx, dtype=torch.float64)
+    N = O.advection(z + 1.7, z, z, box)
+    assert N[0].abs().max() < 1e-13 and N[2].abs().max() < 1e-13
+    u, v, w = (T(x) for x in synth.uniform_velocity(nx, ny, nz, seed=6))
+    nxu, _, nzw = O.advection(u, v, w, box)
+    wt = box.dy[:, None, None]
+    assert abs((nxu * wt).sum()) < 1e-11 * (nxu.abs() * wt).sum()
+    assert abs((nzw * wt).sum()) < 1e-11 * (nzw.abs() * wt).sum()
+
+
+def test_laminar_balance_and_convergence():
+    """Poiseuille U = 1.5(1-y^2) with fx = 3 nu balances the viscous term.  In
+    the interior the discrete residual is a truncation error that falls at
+    second order under refinement (zero on a uniform grid); in the wall cell
+    the mirrored no-slip ghost leaves the known bounded O(1) local error
+    (exactly 1/4 of fx on a uniform grid)."""
+    res = []
+    for gamma in (0.0, 1.0):
+        res = []
+        for ny in (32, 64, 128):
+            box = make_box(4, ny, 4, gamma=gamma)
+            yc = 0.5 * (box.y_faces[1:] + box.y_faces[:-1])
+            u = T(np.broadcast_to((1.5 * (1 - yc ** 2))[:, None, None], (ny, 4, 4)).copy())
+            z = torch.zeros_like(u)
+            nu = 1.0 / 550
+            r = O.momentum_rhs(u, z, z, box, nu, 3 * nu)
+            assert r[1].abs().max() < 1e-15 and r[2].abs().max() < 1e-15
+            rr = r[0][:, 0, 0].numpy() / (3 * nu)
+            assert np.abs(rr[[0, -1]]).max() <= 0.25 + 1e-12
+            res.append(np.abs(rr[1:-1]).max())
+        if gamma == 0.0:
+            assert max(res) < 1e-10
+        else:
+            assert res[1] < 0.3 * res[0] and res[2] < 0.3 * res[1]
+
+
+def test_advection_converges_on_smooth_field():
+    """x-momentum flux divergence of a smooth periodic field on a uniform grid
+    tends to the analytic d(uu)/dx + d(uw)/dz with second-order error."""
+    errs = []
+    for n in (16, 32, 64):
+        box = O.Box(n, 4, n, 2 * np.pi, 2 * np.pi, synth.uniform_faces(4))
+        x = (np.arange(n) + 0.5) * box.dx   # u-face positions x_{i+1/2}
+        xc = np.arange(n) * box.dx
+        zc = np.arange(n) * box.dz
+        zf = (np.arange(n) + 0.5) * box.dz
+        u = np.sin(x)[None, None, :] * np.cos(zc)[None, :, None] * np.ones((4, 1, 1))
+        w = np.cos(xc)[None, None, :] * np.sin(zf)[None, :, None] * np.ones((4, 1, 1))
+        v = np.zeros((4, n, n))
+        N = O.advection(T(u), T(v), T(w), box)[0].numpy()[1]
+        X, Z = np.meshgrid(x, zc)
+        # u = sin x cos z, w = cos x sin z: d(u^2)/dx + d(uw)/dz
+        exact = 2 * np.sin(X) * np.cos(X) * np.cos(Z) ** 2 + np.sin(X) * np.cos(X) * np.cos(2 * Z)
+        errs.append(np.abs(N - exact).max())
+    assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1]
+
+
+# ---------------------------------------------------------------- adjoint
+def test_oracle_gradient_matches_finite_differences():
+    box = make_box(8, 8, 8, gamma=2.0)
+    u, v, w = (T(x) for x in synth.perturbed_poiseuille(8, 8, 8, box.y_faces, seed=2))
+    dt, nu, fx = 1e-2, 1 / 100.0, 3 / 100.0
+    loss, gu, gv, gw = O.rollout_loss_and_grad(u, v, w, box, 2, dt, nu, fx)
+
+    def J(a, b, c):
+        r = O.rollout(a, b, c, box, 2, dt, nu, fx)
+        return 0.5 * sum((q * q).sum() for q in r).item()
+
+    for seed in (1, 2):
+        du, dv, dw = (T(x) for x in synth.random_directions(8, 8, 8, seed))
+        h = 1e-5
+        fd = (J(u + h * du, v + h * dv, w + h * dw) - J(u - h * du, v - h * dv, w - h * dw)) / (2 * h)
+        an = ((gu * du).sum() + (gv * dv).sum() + (gw * dw).sum()).item()
+        assert abs(fd - an) <= 1e-7 * max(abs(fd), abs(an))
