@@ -1,0 +1,163 @@
+/*
+ * chanflow: single-GPU (MI355X, gfx950) pressure-Poisson projection solver for
+ * incompressible channel flow, after the FFT + tridiagonal method of
+ * "A low-communication-overhead parallel method for the 3D incompressible
+ * Navier-Stokes equations" (arXiv 2104.08863).
+ *
+ * Geometry (Section 2, Fig. 1-2): x streamwise and z spanwise are periodic and
+ * uniform (lengths lx, lz; nx, nz cells); y is wall-normal, bounded by two
+ * no-slip walls, with an arbitrary stretched grid given by its ny+1 face
+ * coordinates.  Variables are staggered (Fig. 2): p at cell centres, u on
+ * x-faces, v on y-faces, w on z-faces.
+ *
+ * Every field is a C-order array of shape (ny, nz, nx), x fastest:
+ *   p[j][k][i]  at (x_i,       yc_j,        z_k)
+ *   u[j][k][i]  at (x_{i+1/2}, yc_j,        z_k)
+ *   v[j][k][i]  at (x_i,       y_faces[j+1], z_k)   (v[ny-1] is the top wall:
+ *                                                 its stored values are ignored
+ *                                                 on input and written as 0)
+ *   w[j][k][i]  at (x_i,       yc_j,        z_{k+1/2})
+ * Spectral arrays (test hooks only) are complex (re, im interleaved) of shape
+ * (ny, nx/2+1, nz), z fastest, holding the unnormalised forward transform.
+ *
+ * Conventions for every call:
+ *   - Pointers to fields are DEVICE pointers on the plan's device, 16-byte
+ *     aligned, contiguous; the caller owns them.  y_faces is a HOST pointer.
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL = the
+ *     default stream).  Argument errors are returned synchronously before any
+ *     work is enqueued; a failed launch returns CF_ERR_DEVICE.  Nothing aborts
+ *     or throws across this interface.  cf_last_error() returns a message for
+ *     the last failure on the calling thread.
+ *   - A plan owns all device tables and workspace; calls do not allocate.  A
+ *     plan must not be used from two streams at once.
+ */
+#ifndef CHANFLOW_H
+#define CHANFLOW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cf_plan cf_plan;
+
+typedef enum {
+  CF_OK = 0,
+  CF_ERR_ARG = 1,          /* bad pointer, size, alignment or grid */
+  CF_ERR_UNSUPPORTED = 2,  /* sizes outside the supported transform/partition set */
+  CF_ERR_NOMEM = 3,        /* device allocation failed at plan creation */
+  CF_ERR_DEVICE = 4,       /* a HIP call or launch failed */
+  CF_ERR_NUMERIC = 5       /* non-finite input detected where checked */
+} cf_status;
+
+enum { CF_FP64 = 0, CF_MIXED = 1 };
+
+typedef struct {
+  int precision;      /* CF_FP64 (all arithmetic FP64) or CF_MIXED (FP32 transforms and
+                         bulk wall-normal solves, FP64 low-wavenumber lines and residual) */
+  int n_parts;        /* PDD partitions per wall-normal line; 0 = automatic. ny/n_parts
+                         must be one of 1,2,3,4,6,8,12,16 */
+  double drop_tol;    /* lines whose PDD corner terms are all <= drop_tol use the dropped
+                         (2x2) reduced system; the others the exact one.  < 0 = default
+                         (1e-15 FP64, 1e-7 mixed) */
+  int fp64_kx;        /* CF_MIXED: lines with kx < fp64_kx and min(kz, nz-kz) < fp64_kz */
+  int fp64_kz;        /*   are solved in FP64 (default 4, 4) */
+  int refine_passes;  /* CF_MIXED: FP64 residual + correction solves (default 1) */
+} cf_options;
+
+typedef struct {
+  int nx, ny, nz, precision;
+  int n_parts;            /* partitions per line (P) */
+  int rows_per_part;      /* ny / P */
+  long long n_lines;      /* (nx/2+1) * nz */
+  long long n_drop_lines; /* lines whose corner terms fall below drop_tol */
+  long long n_special;    /* lines solved by whole-line FP64 Thomas */
+  double k2_threshold;    /* modified-wavenumber^2 above which the drop is allowed */
+  size_t workspace_bytes; /* device memory owned by the plan */
+} cf_plan_info;
+
+/* Fill *opt with the defaults. */
+void cf_options_default(cf_options* opt);
+
+/*
+ * Create a plan on the current HIP device (Section 2 problem setup: Eq. (8)-(9)
+ * operator, modified wavenumbers, PDD partitioning of Section 2.2).
+ * nx, nz: even, 2^a or 3*2^a, nx/2 and nz in [2, 2048] (nz >= 2).
+ * ny >= 2 and ny = P*M with M in {1,2,3,4,6,8,12,16} and P <= 64.
+ * y_faces: host, ny+1 strictly increasing finite values (walls at both ends).
+ * opt: NULL for defaults.  On success *out receives the plan; on failure *out is
+ * set to NULL and nothing is leaked.
+ */
+cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, double lz,
+                         const double* y_faces, const cf_options* opt);
+
+/* Release a plan and its device memory (synchronises the device).  NULL-safe. */
+void cf_plan_destroy(cf_plan* plan);
+
+cf_status cf_plan_query(const cf_plan* plan, cf_plan_info* info);
+
+/*
+ * Pressure-Poisson solve (Eq. (7)-(9), Section 3.2 steps (2)-(8)):
+ * p = the unique solution of L_h p = f - mean_W(f) with mean_W(p) = 0, where
+ * L_h = D o G is the staggered 7-point Laplacian (Neumann walls) and
+ * mean_W(q) = sum_j dy_j q_j / (nx nz sum_j dy_j).
+ * f, p: device double arrays (ny, nz, nx); p may alias f.
+ * CF_MIXED plans compute in FP32 with FP64 low-wavenumber lines and the FP64
+ * residual-correction passes of the plan; f and p stay double.
+ */
+cf_status cf_poisson_solve(cf_plan* plan, const double* f, double* p, void* stream);
+
+/*
+ * Divergence right-hand side (Eq. (7), Section 3.2 step (1)):
+ * f = scale * [ (u_i - u_{i-1})/dx + (v_j - v_{j-1})/dy_j + (w_k - w_{k-1})/dz ],
+ * v = 0 on both walls.  u, v, w, f: device double arrays (ny, nz, nx).
+ */
+cf_status cf_divergence(cf_plan* plan, const double* u, const double* v, const double* w,
+                        double* f, double scale, void* stream);
+
+/* Test hook, steps (2)-(4): forward real transform in x then complex transform in z of f
+ * (device double (ny, nz, nx)) into fhat (device complex, plan precision: double pairs
+ * for CF_FP64, float pairs for CF_MIXED; shape (ny, nx/2+1, nz)). */
+cf_status cf_forward_spectral(cf_plan* plan, const double* f, void* fhat, void* stream);
+
+/* Test hook, steps (6)-(8): inverse transforms of phat (layout as above) into p, scaled
+ * by 1/(nx nz).  phat is overwritten. */
+cf_status cf_inverse_spectral(cf_plan* plan, void* phat, double* p, void* stream);
+
+/* Test hook, step (5): solve every wall-normal line of fhat (Eq. (9) with the PDD of
+ * Section 2.2, exact or dropped reduced system per the plan, gauge on the kx=kz=0 line)
+ * into phat.  Same layout and precision as cf_forward_spectral; phat may alias fhat. */
+cf_status cf_solve_spectral(cf_plan* plan, const void* fhat, void* phat, void* stream);
+
+/*
+ * Per-kernel timing with HIP events (measurement support).  While enabled, every
+ * kernel launch of the plan is bracketed by two events recorded on the launch
+ * stream; cf_plan_get_timing synchronises on them and returns the accumulated
+ * device time and launch count of one kernel class since the last reset.
+ */
+enum {
+  CF_K_R2C_X = 0,     /* forward real transform along x (+ fused producers) */
+  CF_K_FFT_Z_FWD = 1, /* forward complex transform along z */
+  CF_K_YSOLVE = 2,    /* PDD wall-normal line solve */
+  CF_K_SPECIAL = 3,   /* whole-line FP64 Thomas (kx=kz=0 and the FP64 set) */
+  CF_K_FFT_Z_INV = 4, /* inverse complex transform along z */
+  CF_K_C2R_X = 5,     /* inverse real transform along x (+ fused consumers) */
+  CF_K_DIVERGENCE = 6,
+  CF_K_COUNT = 7
+};
+cf_status cf_plan_set_timing(cf_plan* plan, int enable);
+cf_status cf_plan_reset_timing(cf_plan* plan);
+cf_status cf_plan_get_timing(cf_plan* plan, int kernel, double* total_ms, long long* launches);
+const char* cf_kernel_name(int kernel);
+
+const char* cf_status_string(cf_status s);
+
+/* Message describing the last error returned on the calling thread ("" if none). */
+const char* cf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHANFLOW_H */

@@ -1,0 +1,156 @@
+"""Python face of the chanflow C ABI: argument checks and pointer marshalling
+for torch tensors on the GPU.  All arithmetic runs in libchanflow.so."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Plan for one grid: nx x ny x nz cells, periodic lengths lx, lz, wall-normal
+    faces y_faces (ny+1 values).  precision: 'fp64' or 'mixed'."""
+
+    def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
+                 precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
+                 fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
+                 device=None):
+        lib = L.lib()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.nkx = self.nx // 2 + 1
+        self.lx, self.lz = float(lx), float(lz)
+        yf = np.ascontiguousarray(np.asarray(y_faces, dtype=np.float64))
+        if yf.shape != (self.ny + 1,):
+            raise ValueError(f"y_faces must have ny+1 = {self.ny + 1} values, got {yf.shape}")
+        self.y_faces = yf
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        self.precision = precision
+        opt = L.cf_options()
+        lib.cf_options_default(C.byref(opt))
+        opt.precision = L.CF_FP64 if precision == "fp64" else L.CF_MIXED
+        opt.n_parts = int(n_parts)
+        opt.drop_tol = float(drop_tol)
+        opt.fp64_kx = int(fp64_kx)
+        opt.fp64_kz = int(fp64_kz)
+        opt.refine_passes = int(refine_passes)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.cf_plan_create(C.byref(self._h), self.nx, self.ny, self.nz, self.lx, self.lz,
+                                    yf.ctypes.data_as(C.POINTER(C.c_double)), C.byref(opt))
+        L.check(st, "cf_plan_create")
+        self.spec_dtype = torch.complex128 if precision == "fp64" else torch.complex64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            L.lib().cf_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ info
+    def info(self) -> dict:
+        inf = L.cf_plan_info()
+        L.check(L.lib().cf_plan_query(self._h, C.byref(inf)), "cf_plan_query")
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    # ------------------------------------------------------------------ timing
+    def set_timing(self, enable: bool):
+        L.check(L.lib().cf_plan_set_timing(self._h, int(bool(enable))), "cf_plan_set_timing")
+
+    def reset_timing(self):
+        L.check(L.lib().cf_plan_reset_timing(self._h), "cf_plan_reset_timing")
+
+    def timings(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last reset."""
+        out = {}
+        for k, name in enumerate(L.KERNELS):
+            ms, n = C.c_double(), C.c_longlong()
+            L.check(L.lib().cf_plan_get_timing(self._h, k, C.byref(ms), C.byref(n)), "cf_plan_get_timing")
+            out[name] = (ms.value, n.value)
+        return out
+
+    # ------------------------------------------------------------------ checks
+    @property
+    def shape(self):
+        return (self.ny, self.nz, self.nx)
+
+    @property
+    def spec_shape(self):
+        return (self.ny, self.nkx, self.nz)
+
+    def _field(self, t: torch.Tensor, name: str, dtype=torch.float64):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device:
+            raise ValueError(f"{name} must be on {self.device}, got {t.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"{name} must have shape {self.shape}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _spec(self, t: torch.Tensor, name: str):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device != self.device or t.dtype != self.spec_dtype:
+            raise TypeError(f"{name} must be {self.spec_dtype} on {self.device}")
+        if tuple(t.shape) != self.spec_shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {self.spec_shape}")
+        return t
+
+    def _new(self, dtype=torch.float64):
+        return torch.empty(self.shape, dtype=dtype, device=self.device)
+
+    # ------------------------------------------------------------------ calls
+    def poisson_solve(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._field(f, "f")
+        out = self._new() if out is None else self._field(out, "out")
+        L.check(L.lib().cf_poisson_solve(self._h, _ptr(f), _ptr(out), _stream()), "cf_poisson_solve")
+        return out
+
+    def divergence(self, u, v, w, scale: float = 1.0, out=None) -> torch.Tensor:
+        for t, n in ((u, "u"), (v, "v"), (w, "w")):
+            self._field(t, n)
+        out = self._new() if out is None else self._field(out, "out")
+        L.check(L.lib().cf_divergence(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out), float(scale),
+                                      _stream()), "cf_divergence")
+        return out
+
+    def forward_spectral(self, f: torch.Tensor, out=None) -> torch.Tensor:
+        self._field(f, "f")
+        out = torch.empty(self.spec_shape, dtype=self.spec_dtype, device=self.device) if out is None \
+            else self._spec(out, "out")
+        L.check(L.lib().cf_forward_spectral(self._h, _ptr(f), _ptr(out), _stream()), "cf_forward_spectral")
+        return out
+
+    def inverse_spectral(self, fhat: torch.Tensor, out=None) -> torch.Tensor:
+        """Inverse transforms; fhat is overwritten."""
+        self._spec(fhat, "fhat")
+        out = self._new() if out is None else self._field(out, "out")
+        L.check(L.lib().cf_inverse_spectral(self._h, _ptr(fhat), _ptr(out), _stream()), "cf_inverse_spectral")
+        return out
+
+    def solve_spectral(self, fhat: torch.Tensor, out=None) -> torch.Tensor:
+        self._spec(fhat, "fhat")
+        out = torch.empty_like(fhat) if out is None else self._spec(out, "out")
+        L.check(L.lib().cf_solve_spectral(self._h, _ptr(fhat), _ptr(out), _stream()), "cf_solve_spectral")
+        return out

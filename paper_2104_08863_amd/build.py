@@ -1,0 +1,84 @@
+"""Build the chanflow HIP library (gfx950) and its host-emulation companion.
+
+    python -m paper_2104_08863_amd.build        # or: from ... import build; build.build()
+
+Outputs (in this package directory, not tracked by git):
+  libchanflow.so       - the HIP kernels + C ABI of include/chanflow.h
+  libchanflow_host.so  - host-only build of the kernels' per-thread math
+                         (Stockham passes, PDD local/reduced solves) used by
+                         the CPU tests
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(PKG, "csrc")
+ROOT = os.path.dirname(PKG)
+BUILD = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libchanflow.so")
+HOSTLIB = os.path.join(PKG, "libchanflow_host.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    # keep the compiler from emitting packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+]
+HOST_SOURCES = ["cf_host_emul.cpp"]
+
+
+def _hip_sources():
+    return sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in r.stdout.splitlines() if "packed-fp32-ops" not in l)
+    return r.returncode, out
+
+
+def build(verbose: bool = True, jobs: int | None = None) -> None:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = _hip_sources()
+    objs = [os.path.join(BUILD, s[:-4] + ".o") for s in srcs]
+    jobs = jobs or min(8, max(1, os.cpu_count() or 1))
+
+    def comp(src_obj):
+        src, obj = src_obj
+        return src, _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(comp, zip(srcs, objs)))
+    failed = [(s, o) for s, (rc, o) in results if rc != 0]
+    for s, (rc, o) in results:
+        if verbose and o.strip():
+            print(f"[{s}]\n{o}", file=sys.stderr)
+    if failed:
+        raise RuntimeError("HIP compilation failed: " + ", ".join(s for s, _ in failed)
+                           + "\n" + "\n".join(o for _, o in failed))
+    tmp = LIB + ".tmp"
+    rc, o = _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    if rc != 0:
+        raise RuntimeError("link failed:\n" + o)
+    os.replace(tmp, LIB)
+    # host emulation library (plain C++)
+    gxx = shutil.which("g++") or "g++"
+    tmp = HOSTLIB + ".tmp"
+    rc, o = _run([gxx, "-O2", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+                  "-I", CSRC, "-o", tmp] + [os.path.join(CSRC, s) for s in HOST_SOURCES])
+    if rc != 0:
+        raise RuntimeError("host emulation build failed:\n" + o)
+    os.replace(tmp, HOSTLIB)
+    if verbose:
+        print(f"built {LIB} and {HOSTLIB}", file=sys.stderr)
+
+
+if __name__ == "__main__":
+    build()

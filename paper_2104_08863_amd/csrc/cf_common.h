@@ -1,0 +1,45 @@
+// Shared device/host helpers for the chanflow HIP kernels: a plain complex
+// type and the handful of operations the transforms and solves need.
+//
+// Everything here is usable from host code as well, so the per-thread math of
+// the kernels can be exercised on the CPU.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define CF_HD __host__ __device__ __forceinline__
+#else
+#define CF_HD inline
+#endif
+
+namespace cf {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T re, im;
+};
+
+template <typename T> CF_HD cx<T> mk(T r, T i) { cx<T> z; z.re = r; z.im = i; return z; }
+template <typename T> CF_HD cx<T> operator+(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T> CF_HD cx<T> operator-(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T> CF_HD cx<T> operator*(cx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T> CF_HD cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+// a * conj(b)
+template <typename T> CF_HD cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk(a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im);
+}
+template <typename T> CF_HD cx<T> conj(cx<T> a) { return mk(a.re, -a.im); }
+// multiply by -i (forward sign) or +i (inverse sign)
+template <bool INV, typename T> CF_HD cx<T> mul_mi(cx<T> a) {
+  return INV ? mk(-a.im, a.re) : mk(a.im, -a.re);
+}
+
+template <typename T> CF_HD T cf_max(T a, T b) { return a > b ? a : b; }
+template <typename T> CF_HD T cf_min(T a, T b) { return a < b ? a : b; }
+
+}  // namespace cf

@@ -1,0 +1,236 @@
+// Batched LDS Stockham FFT kernels for the periodic directions.
+//
+// Spectral layout (owned by the plan): complex, [ny][nx/2+1][nz], z fastest.
+//   * k_fft_z     : complex transform of every contiguous z-line, in place.
+//   * k_r2c_x     : real transform of K consecutive x-rows (fixed j, rows
+//                   k0..k0+K-1) through a half-length complex transform,
+//                   written transposed into the spectral layout (for every kx
+//                   a contiguous run of K values of kz).
+//   * k_c2r_x     : the inverse, reading the transposed tile.
+// Data enter the first radix pass straight from global memory and leave the
+// last pass straight to global memory (or to LDS where the real<->half-complex
+// step needs partner elements); intermediate passes exchange through LDS.
+#pragma once
+
+#include "cf_fft.h"
+
+namespace cf {
+
+template <int N>
+struct FftT {
+  static constexpr RadixPlan P = make_radix_plan(N);
+  static constexpr int E = P.e;
+  static constexpr int TPL = N / E;
+  static constexpr int R0 = P.r[0];
+  static constexpr int RL = P.r[P.np - 1];
+};
+
+// Runs passes PASS..np-1 on the registers x (pass PASS input order on entry,
+// last-pass output order on exit).  sl: this line's LDS (N slots).  Every
+// thread of the block must call this (it contains block barriers).
+template <int N, bool INV, typename T, int PASS>
+__device__ __forceinline__ void fft_passes(cx<T>* x, int t, cx<T>* sl, const cx<T>* __restrict__ tw) {
+  constexpr RadixPlan P = make_radix_plan(N);
+  constexpr int E = P.e;
+  constexpr int TPL = N / E;
+  constexpr int R = P.r[PASS];
+  constexpr int NS = plan_ns(N, PASS);
+  if constexpr (PASS > 0) {
+    constexpr int RP = P.r[PASS - 1];
+    constexpr int NSP = plan_ns(N, PASS - 1);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E / RP; ++q) {
+      const int b = t + q * TPL;
+#pragma unroll
+      for (int r = 0; r < RP; ++r) sl[st_out(RP, NSP, b, r)] = x[q * RP + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+      const int b = t + q * TPL;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[q * R + r] = sl[st_in(N, R, b, r)];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < E / R; ++q) pass_group<N, R, NS, INV>(x + q * R, t + q * TPL, tw);
+  if constexpr (PASS + 1 < P.np) fft_passes<N, INV, T, PASS + 1>(x, t, sl, tw);
+}
+
+constexpr int lds_lines(int n, int tpl, int esize, int budget) {
+  int l = 256 / tpl;
+  if (l < 1) l = 1;
+  while (l > 1 && l * n * esize > budget) l /= 2;
+  return l;
+}
+
+// ---------------------------------------------------------------- z (contiguous lines)
+template <typename T, int N>
+struct ZCfg {
+  static constexpr int LPB = lds_lines(N, FftT<N>::TPL, int(sizeof(cx<T>)), 32768);
+  static constexpr int THREADS = LPB * FftT<N>::TPL;
+};
+
+template <typename T, int N, bool INV>
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
+k_fft_z(cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, long nlines) {
+  using F = FftT<N>;
+  constexpr int LPB = ZCfg<T, N>::LPB;
+  __shared__ cx<T> lds[LPB * N];
+  const int tl = threadIdx.x % F::TPL;
+  const int lb = threadIdx.x / F::TPL;
+  const long line = (long)blockIdx.x * LPB + lb;
+  const bool ok = line < nlines;
+  cx<T>* g = data + (ok ? line : 0) * N;
+  cx<T> x[F::E];
+#pragma unroll
+  for (int q = 0; q < F::E / F::R0; ++q) {
+    const int b = tl + q * F::TPL;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? g[st_in(N, F::R0, b, r)] : mk(T(0), T(0));
+  }
+  fft_passes<N, INV, T, 0>(x, tl, lds + lb * N, tw);
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < F::E / F::RL; ++q) {
+      const int b = tl + q * F::TPL;
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) g[b + r * (N / F::RL)] = x[q * F::RL + r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- x (real rows, transposed spectrum)
+template <typename T, int NH>
+struct XCfg {
+  // rows per block: aim for 128-byte runs of kz in the transposed spectrum
+  static constexpr int KWANT = int(128 / sizeof(cx<T>));
+  static constexpr int S = NH + 1;  // padded LDS row stride (also holds kx = NH)
+  static constexpr int kfit(int k) {
+    return (k > 1 && (k * S * int(sizeof(cx<T>)) > 73728 || k * FftT<NH>::TPL > 1024)) ? kfit(k / 2) : k;
+  }
+  static constexpr int K = kfit(KWANT);
+  static constexpr int THREADS = K * FftT<NH>::TPL;
+};
+
+// Row sources for the forward real transform: element pair (x_{2m}, x_{2m+1})
+// of row (j, k).
+template <typename T, typename Tin>
+struct SrcPlain {
+  const Tin* __restrict__ f;
+  int nx, nz;
+  __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
+    const cx<Tin>* row = reinterpret_cast<const cx<Tin>*>(f + ((long)j * nz + k) * nx);
+    cx<Tin> v = row[m];
+    return mk(T(v.re), T(v.im));
+  }
+};
+
+template <typename T, int NH, typename Src>
+__global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
+k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ twp,
+        int ny, int nz) {
+  using F = FftT<NH>;
+  constexpr int K = XCfg<T, NH>::K;
+  constexpr int S = XCfg<T, NH>::S;
+  constexpr int NKX = NH + 1;
+  __shared__ cx<T> lds[K * S];
+  const int nzb = (nz + K - 1) / K;
+  const int j = blockIdx.x / nzb;
+  const int k0 = (blockIdx.x % nzb) * K;
+  const int tl = threadIdx.x % F::TPL;
+  const int rr = threadIdx.x / F::TPL;
+  const int k = k0 + rr;
+  const bool ok = k < nz;
+  cx<T> x[F::E];
+#pragma unroll
+  for (int q = 0; q < F::E / F::R0; ++q) {
+    const int b = tl + q * F::TPL;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? src.pair(j, k, st_in(NH, F::R0, b, r)) : mk(T(0), T(0));
+  }
+  cx<T>* sl = lds + rr * S;
+  fft_passes<NH, false, T, 0>(x, tl, sl, tw);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < F::E / F::RL; ++q) {
+    const int b = tl + q * F::TPL;
+#pragma unroll
+    for (int r = 0; r < F::RL; ++r) sl[b + r * (NH / F::RL)] = x[q * F::RL + r];
+  }
+  __syncthreads();
+  const long plane = (long)j * NKX;
+  for (int idx = threadIdx.x; idx < NKX * K; idx += blockDim.x) {
+    const int r = idx % K;
+    const int kx = idx / K;
+    if (k0 + r < nz) {
+      const cx<T>* row = lds + r * S;
+      cx<T> X = r2c_post(row[kx == NH ? 0 : kx], row[kx == 0 ? 0 : NH - kx], twp[kx]);
+      spec[(plane + kx) * nz + k0 + r] = X;
+    }
+  }
+}
+
+// Row sinks for the inverse real transform: receives (x_{2m}, x_{2m+1}) of row
+// (j, k), already scaled.
+template <typename T, typename Tout>
+struct DstPlain {
+  Tout* __restrict__ p;
+  int nx, nz;
+  __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
+    cx<Tout>* row = reinterpret_cast<cx<Tout>*>(p + ((long)j * nz + k) * nx);
+    row[m] = mk(Tout(v.re), Tout(v.im));
+  }
+};
+
+template <typename T, int NH, typename Dst>
+__global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
+k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* __restrict__ tw,
+        const cx<T>* __restrict__ twp, int ny, int nz, T scale) {
+  using F = FftT<NH>;
+  constexpr int K = XCfg<T, NH>::K;
+  constexpr int S = XCfg<T, NH>::S;
+  constexpr int NKX = NH + 1;
+  __shared__ cx<T> lds[K * S];
+  const int nzb = (nz + K - 1) / K;
+  const int j = blockIdx.x / nzb;
+  const int k0 = (blockIdx.x % nzb) * K;
+  const long plane = (long)j * NKX;
+  for (int idx = threadIdx.x; idx < NKX * K; idx += blockDim.x) {
+    const int r = idx % K;
+    const int kx = idx / K;
+    lds[r * S + kx] = (k0 + r < nz) ? spec[(plane + kx) * nz + k0 + r] : mk(T(0), T(0));
+  }
+  __syncthreads();
+  const int tl = threadIdx.x % F::TPL;
+  const int rr = threadIdx.x / F::TPL;
+  const int k = k0 + rr;
+  cx<T>* sl = lds + rr * S;
+  cx<T> x[F::E];
+#pragma unroll
+  for (int q = 0; q < F::E / F::R0; ++q) {
+    const int b = tl + q * F::TPL;
+#pragma unroll
+    for (int r = 0; r < F::R0; ++r) {
+      const int m = st_in(NH, F::R0, b, r);
+      cx<T> a = sl[m], bb = sl[NH - m];
+      if (m == 0) {
+        a.im = T(0);
+        bb.im = T(0);
+      }
+      x[q * F::R0 + r] = c2r_pre(a, bb, twp[m]);
+    }
+  }
+  fft_passes<NH, true, T, 0>(x, tl, sl, tw);
+  if (k < nz) {
+#pragma unroll
+    for (int q = 0; q < F::E / F::RL; ++q) {
+      const int b = tl + q * F::TPL;
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r) dst.put(j, k, b + r * (NH / F::RL), x[q * F::RL + r] * scale);
+    }
+  }
+}
+
+}  // namespace cf

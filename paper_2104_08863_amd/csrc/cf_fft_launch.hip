@@ -1,0 +1,109 @@
+// Length dispatch and launch of the periodic-direction transforms.
+#include "cf_fft_kernels.h"
+#include "cf_internal.h"
+
+namespace cf {
+
+#define CF_FOR_EACH_LEN(X) \
+  X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) \
+  X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+bool fft_len_compiled(int n) {
+  switch (n) {
+#define CF_CASE(N) case N:
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+template <typename T, int N>
+static hipError_t fft_z_n(bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s) {
+  using C = ZCfg<T, N>;
+  const long blocks = (nlines + C::LPB - 1) / C::LPB;
+  if (blocks <= 0) return hipSuccess;
+  if (inv)
+    hipLaunchKernelGGL((k_fft_z<T, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, data, tw, nlines);
+  else
+    hipLaunchKernelGGL((k_fft_z<T, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, data, tw, nlines);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_z(int n, bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s) {
+  switch (n) {
+#define CF_CASE(N) \
+  case N:          \
+    return fft_z_n<T, N>(inv, data, tw, nlines, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int NH, typename Src>
+static hipError_t r2c_n(Src src, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
+                        hipStream_t s) {
+  using C = XCfg<T, NH>;
+  const long blocks = (long)ny * ((nz + C::K - 1) / C::K);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_r2c_x<T, NH, Src>), dim3(blocks), dim3(C::THREADS), 0, s, src, spec, tw, twp,
+                     ny, nz);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_r2c_plain(int nh, const double* f, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, hipStream_t s) {
+  SrcPlain<T, double> src{f, 2 * nh, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return r2c_n<T, N>(src, spec, tw, twp, ny, nz, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int NH, typename Dst>
+static hipError_t c2r_n(const cx<T>* spec, Dst dst, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
+                        T scale, hipStream_t s) {
+  using C = XCfg<T, NH>;
+  const long blocks = (long)ny * ((nz + C::K - 1) / C::K);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_c2r_x<T, NH, Dst>), dim3(blocks), dim3(C::THREADS), 0, s, spec, dst, tw, twp,
+                     ny, nz, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, T scale, hipStream_t s) {
+  DstPlain<T, double> dst{p, 2 * nh, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return c2r_n<T, N>(spec, dst, tw, twp, ny, nz, scale, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+#define CF_INST(T)                                                                                   \
+  template hipError_t launch_fft_z<T>(int, bool, cx<T>*, const cx<T>*, long, hipStream_t);           \
+  template hipError_t launch_r2c_plain<T>(int, const double*, cx<T>*, const cx<T>*, const cx<T>*, int, \
+                                          int, hipStream_t);                                         \
+  template hipError_t launch_c2r_plain<T>(int, const cx<T>*, double*, const cx<T>*, const cx<T>*, int, \
+                                          int, T, hipStream_t);
+CF_INST(double)
+CF_INST(float)
+#undef CF_INST
+
+}  // namespace cf

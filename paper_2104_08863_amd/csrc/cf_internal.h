@@ -1,0 +1,55 @@
+// Internal launch interface between the plan/ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cf_common.h"
+
+namespace cf {
+
+// Transform lengths with compiled kernels: 2^a and 3*2^a from 2 to 2048.
+bool fft_len_compiled(int n);
+
+template <typename T>
+hipError_t launch_fft_z(int n, bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s);
+
+// Forward real transform of rows of a plain array (Tin = double, stored as
+// (ny, nz, nx)) into the transposed spectrum.
+template <typename T>
+hipError_t launch_r2c_plain(int nh, const double* f, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, hipStream_t s);
+
+// Divergence of (u, v, w) times `scale`, fused into the forward real transform.
+template <typename T>
+hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double* w,
+                          const double* rdy, double rdx, double rdz, double scale, cx<T>* spec,
+                          const cx<T>* tw, const cx<T>* twp, int ny, int nz, hipStream_t s);
+
+template <typename T>
+hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, T scale, hipStream_t s);
+
+struct YLaunch {
+  int ny, nz, nkx, P, M;
+  long nlines;
+  int skip_kx, skip_kz;
+};
+
+template <typename T>
+hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,
+                         const T* kx2, const T* kz2, T k2drop, hipStream_t s);
+
+template <typename T>
+hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* c,
+                                const double* dy, const double* kx2, const double* kz2,
+                                const int* lines, int n_lines, double* scratch, int ny, int nz,
+                                int nkx, hipStream_t s);
+
+bool ysolve_m_compiled(int m);
+
+// Plain divergence (test hook): f = scale * D(u, v, w).
+hipError_t launch_divergence(const double* u, const double* v, const double* w, double* f,
+                             const double* rdy, double rdx, double rdz, double scale, int nx,
+                             int ny, int nz, hipStream_t s);
+
+}  // namespace cf

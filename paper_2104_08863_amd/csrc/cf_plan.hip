@@ -1,0 +1,624 @@
+// Plan creation and the C ABI of chanflow (see include/chanflow.h).
+//
+// The plan turns the problem statement of Section 2 into device tables: the
+// wall-normal coefficients of the staggered Laplacian, the modified
+// wavenumbers of Eq. (9) (eigenvalues of the periodic second difference), the
+// twiddle tables of the transforms, the PDD partitioning of Section 2.2 with
+// the k^2 threshold above which the corner terms of Eq. (21) are negligible,
+// and the list of lines solved by whole-line FP64 Thomas.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/chanflow.h"
+#include "cf_fft.h"
+#include "cf_internal.h"
+#include "cf_pdd.h"
+
+namespace cf {
+size_t ysolve_lds_needed(int ny, int P, bool fp64);
+}
+
+using cf::cx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+cf_status fail(cf_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+cf_status dev_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return CF_ERR_DEVICE;
+}
+
+// exp(-2 pi i m / n) from the exactly reduced ratio m/n.
+cx<double> unit_root(long m, long n) {
+  m %= n;
+  if (m < 0) m += n;
+  const long double t = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)n;
+  return cf::mk((double)cosl(t), (double)-sinl(t));
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct cf_plan {
+  int nx, ny, nz, nkx, nh;
+  double lx, lz, dx, dz;
+  cf_options opt;
+  int device;
+  int P, M;
+  double k2drop;
+  long long n_drop;
+  std::vector<double> yf, dy, dyc, a, c, kx2, kz2;
+  std::vector<int> special;
+  std::vector<DevBuf> allocs;
+  size_t bytes = 0;
+  // device tables (FP64 and FP32 copies)
+  double *d_a = nullptr, *d_c = nullptr, *d_dy = nullptr, *d_rdy = nullptr, *d_kx2 = nullptr,
+         *d_kz2 = nullptr;
+  float *s_a = nullptr, *s_c = nullptr, *s_kx2 = nullptr, *s_kz2 = nullptr;
+  cx<double>*tw_z64 = nullptr, *tw_x64 = nullptr, *twp64 = nullptr;
+  cx<float>*tw_z32 = nullptr, *tw_x32 = nullptr, *twp32 = nullptr;
+  int* d_special = nullptr;
+  double* d_special_scratch = nullptr;
+  void* spec = nullptr;  // spectral workspace, (ny, nkx, nz) complex of the bulk precision
+  bool mixed() const { return opt.precision == CF_MIXED; }
+  // per-kernel event timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // created on demand, reused after each harvest
+  size_t ev_used = 0;
+  struct Pending {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  double acc_ms[CF_K_COUNT] = {0};
+  long long acc_n[CF_K_COUNT] = {0};
+};
+
+namespace {
+
+template <typename T>
+cf_status dalloc(cf_plan* pl, T** out, size_t count) {
+  void* p = nullptr;
+  const size_t nb = std::max<size_t>(count * sizeof(T), 256);
+  hipError_t e = hipMalloc(&p, nb);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CF_ERR_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed");
+  }
+  pl->allocs.push_back(DevBuf{p, nb});
+  pl->bytes += nb;
+  *out = static_cast<T*>(p);
+  return CF_OK;
+}
+
+template <typename T>
+cf_status upload(cf_plan* pl, T** out, const std::vector<T>& h) {
+  cf_status s = dalloc(pl, out, h.size());
+  if (s != CF_OK) return s;
+  hipError_t e = hipMemcpy(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return dev_fail(e, "hipMemcpy (plan tables)");
+  return CF_OK;
+}
+
+void free_all(cf_plan* pl) {
+  if (!pl->allocs.empty() || !pl->events.empty()) (void)hipDeviceSynchronize();
+  for (auto& b : pl->allocs) (void)hipFree(b.p);
+  pl->allocs.clear();
+  for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+  pl->events.clear();
+  pl->pending.clear();
+}
+
+hipError_t next_event(cf_plan* pl, hipEvent_t* ev) {
+  if (pl->ev_used == pl->events.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pl->events.push_back(e);
+  }
+  *ev = pl->events[pl->ev_used++];
+  return hipSuccess;
+}
+
+// Launch through `launch` (returning hipError_t), bracketed by events when the
+// plan's timing is on.
+template <class F>
+cf_status timed(cf_plan* pl, int cls, hipStream_t s, const char* what, F&& launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (pl->timing) {
+    hipError_t r = next_event(pl, &a);
+    if (r == hipSuccess) r = next_event(pl, &b);
+    if (r == hipSuccess) r = hipEventRecord(a, s);
+    if (r != hipSuccess) return dev_fail(r, "timing event");
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return dev_fail(e, what);
+  if (pl->timing) {
+    hipError_t r = hipEventRecord(b, s);
+    if (r != hipSuccess) return dev_fail(r, "timing event");
+    pl->pending.push_back(cf_plan::Pending{cls, a, b});
+  }
+  return CF_OK;
+}
+
+cf_status harvest(cf_plan* pl) {
+  for (auto& p : pl->pending) {
+    hipError_t r = hipEventSynchronize(p.b);
+    if (r != hipSuccess) return dev_fail(r, "hipEventSynchronize");
+    float ms = 0.f;
+    r = hipEventElapsedTime(&ms, p.a, p.b);
+    if (r != hipSuccess) return dev_fail(r, "hipEventElapsedTime");
+    pl->acc_ms[p.cls] += ms;
+    pl->acc_n[p.cls] += 1;
+  }
+  pl->pending.clear();
+  pl->ev_used = 0;
+  return CF_OK;
+}
+
+// Largest corner term of Eq. (21) over the interior partitions, for one k^2.
+double corner_delta(const cf_plan* pl, double k2) {
+  const int P = pl->P, M = pl->M;
+  double delta = 0.0;
+  std::vector<cx<double>> d(M);
+  std::vector<double> v(M), w(M);
+  for (int i = 1; i + 1 < P; ++i) {
+    std::fill(d.begin(), d.end(), cf::mk(0.0, 0.0));
+    const double* ar = pl->a.data() + i * M;
+    const double* cr = pl->c.data() + i * M;
+    switch (M) {
+#define CF_CASE(MM) \
+  case MM:          \
+    cf::pdd_local<MM, double>(ar, cr, k2, d.data(), v.data(), w.data()); \
+    break;
+      CF_CASE(1) CF_CASE(2) CF_CASE(3) CF_CASE(4) CF_CASE(6) CF_CASE(8) CF_CASE(12) CF_CASE(16)
+#undef CF_CASE
+      default:
+        return INFINITY;
+    }
+    delta = std::max(delta, std::max(std::fabs(v[M - 1]), std::fabs(w[0])));
+  }
+  return delta;
+}
+
+int auto_parts(int ny) {
+  // fewest partitions with at most 16 rows each, preferring powers of two
+  for (int P = 1; P <= 64; P *= 2)
+    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P)) return P;
+  for (int P = 1; P <= 64; ++P)
+    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P)) return P;
+  return 0;
+}
+
+bool parts_ok(int ny, int P) { return P >= 1 && P <= 64 && ny % P == 0 && cf::ysolve_m_compiled(ny / P); }
+
+cf_status check_plan(const cf_plan* pl) {
+  if (!pl) return fail(CF_ERR_ARG, "plan is NULL");
+  return CF_OK;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+cf_status check_ptr(const void* p, const char* name) {
+  if (!p) return fail(CF_ERR_ARG, std::string(name) + " is NULL");
+  if (!aligned16(p)) return fail(CF_ERR_ARG, std::string(name) + " is not 16-byte aligned");
+  return CF_OK;
+}
+
+#define CF_TRY(x)                     \
+  do {                                \
+    cf_status _s = (x);               \
+    if (_s != CF_OK) return _s;       \
+  } while (0)
+#define CF_HIP(x, what)                          \
+  do {                                           \
+    hipError_t _e = (x);                         \
+    if (_e != hipSuccess) return dev_fail(_e, what); \
+  } while (0)
+
+// ---------------------------------------------------------------- pipelines
+template <typename T>
+struct Tabs;
+template <>
+struct Tabs<double> {
+  static const double* a(const cf_plan* p) { return p->d_a; }
+  static const double* c(const cf_plan* p) { return p->d_c; }
+  static const double* kx2(const cf_plan* p) { return p->d_kx2; }
+  static const double* kz2(const cf_plan* p) { return p->d_kz2; }
+  static const cx<double>* twz(const cf_plan* p) { return p->tw_z64; }
+  static const cx<double>* twx(const cf_plan* p) { return p->tw_x64; }
+  static const cx<double>* twp(const cf_plan* p) { return p->twp64; }
+};
+template <>
+struct Tabs<float> {
+  static const float* a(const cf_plan* p) { return p->s_a; }
+  static const float* c(const cf_plan* p) { return p->s_c; }
+  static const float* kx2(const cf_plan* p) { return p->s_kx2; }
+  static const float* kz2(const cf_plan* p) { return p->s_kz2; }
+  static const cx<float>* twz(const cf_plan* p) { return p->tw_z32; }
+  static const cx<float>* twx(const cf_plan* p) { return p->tw_x32; }
+  static const cx<float>* twp(const cf_plan* p) { return p->twp32; }
+};
+
+template <typename T>
+cf_status forward_t(cf_plan* pl, const double* f, cx<T>* spec, hipStream_t s) {
+  using TB = Tabs<T>;
+  CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c launch", [&] {
+    return cf::launch_r2c_plain<T>(pl->nh, f, spec, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+  }));
+  CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+    return cf::launch_fft_z<T>(pl->nz, false, spec, TB::twz(pl), (long)pl->ny * pl->nkx, s);
+  }));
+  return CF_OK;
+}
+
+template <typename T>
+cf_status inverse_t(cf_plan* pl, cx<T>* spec, double* p, hipStream_t s) {
+  using TB = Tabs<T>;
+  CF_TRY(timed(pl, CF_K_FFT_Z_INV, s, "z ifft launch", [&] {
+    return cf::launch_fft_z<T>(pl->nz, true, spec, TB::twz(pl), (long)pl->ny * pl->nkx, s);
+  }));
+  const T scale = T(1.0 / ((double)pl->nx * (double)pl->nz));
+  CF_TRY(timed(pl, CF_K_C2R_X, s, "c2r launch", [&] {
+    return cf::launch_c2r_plain<T>(pl->nh, spec, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scale, s);
+  }));
+  return CF_OK;
+}
+
+template <typename T>
+cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
+  using TB = Tabs<T>;
+  cf::YLaunch y;
+  y.ny = pl->ny;
+  y.nz = pl->nz;
+  y.nkx = pl->nkx;
+  y.P = pl->P;
+  y.M = pl->M;
+  y.nlines = (long)pl->nkx * pl->nz;
+  y.skip_kx = pl->mixed() ? pl->opt.fp64_kx : 0;
+  y.skip_kz = pl->mixed() ? pl->opt.fp64_kz : 0;
+  const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
+  CF_TRY(timed(pl, CF_K_YSOLVE, s, "y-solve launch", [&] {
+    return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
+  }));
+  CF_TRY(timed(pl, CF_K_SPECIAL, s, "special-line launch", [&] {
+    return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_c, pl->d_dy, pl->d_kx2, pl->d_kz2,
+                                       pl->d_special, (int)pl->special.size(), pl->d_special_scratch,
+                                       pl->ny, pl->nz, pl->nkx, s);
+  }));
+  return CF_OK;
+}
+
+template <typename T>
+cf_status poisson_t(cf_plan* pl, const double* f, double* p, hipStream_t s) {
+  cx<T>* spec = static_cast<cx<T>*>(pl->spec);
+  CF_TRY(forward_t<T>(pl, f, spec, s));
+  CF_TRY(solve_t<T>(pl, spec, spec, s));
+  CF_TRY(inverse_t<T>(pl, spec, p, s));
+  return CF_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void cf_options_default(cf_options* opt) {
+  if (!opt) return;
+  opt->precision = CF_FP64;
+  opt->n_parts = 0;
+  opt->drop_tol = -1.0;
+  opt->fp64_kx = 4;
+  opt->fp64_kz = 4;
+  opt->refine_passes = 1;
+}
+
+const char* cf_status_string(cf_status s) {
+  switch (s) {
+    case CF_OK: return "ok";
+    case CF_ERR_ARG: return "invalid argument";
+    case CF_ERR_UNSUPPORTED: return "unsupported size";
+    case CF_ERR_NOMEM: return "out of device memory";
+    case CF_ERR_DEVICE: return "device error";
+    case CF_ERR_NUMERIC: return "non-finite values";
+  }
+  return "unknown status";
+}
+
+const char* cf_last_error(void) { return g_last_error.c_str(); }
+
+cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, double lz,
+                         const double* y_faces, const cf_options* opt_in) {
+  g_last_error.clear();
+  if (!out) return fail(CF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  cf_options opt;
+  cf_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  if (opt.precision != CF_FP64 && opt.precision != CF_MIXED) return fail(CF_ERR_ARG, "precision must be CF_FP64 or CF_MIXED");
+  if (nx < 4 || nx % 2 != 0) return fail(CF_ERR_ARG, "nx must be even and >= 4");
+  if (nz < 2) return fail(CF_ERR_ARG, "nz must be >= 2");
+  if (ny < 2) return fail(CF_ERR_ARG, "ny must be >= 2");
+  if (!(lx > 0.0) || !(lz > 0.0) || !std::isfinite(lx) || !std::isfinite(lz)) return fail(CF_ERR_ARG, "lx, lz must be finite and > 0");
+  if (!y_faces) return fail(CF_ERR_ARG, "y_faces is NULL");
+  for (int j = 0; j <= ny; ++j)
+    if (!std::isfinite(y_faces[j])) return fail(CF_ERR_ARG, "y_faces holds a non-finite value");
+  for (int j = 0; j < ny; ++j)
+    if (!(y_faces[j + 1] > y_faces[j])) return fail(CF_ERR_ARG, "y_faces must be strictly increasing");
+  if (!cf::fft_len_compiled(nx / 2)) return fail(CF_ERR_UNSUPPORTED, "nx/2 must be 2^a or 3*2^a in [2, 2048]");
+  if (!cf::fft_len_compiled(nz)) return fail(CF_ERR_UNSUPPORTED, "nz must be 2^a or 3*2^a in [2, 2048]");
+  int P = opt.n_parts;
+  if (P == 0) P = auto_parts(ny);
+  if (P == 0 || !parts_ok(ny, P))
+    return fail(CF_ERR_UNSUPPORTED, "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16}");
+  if (opt.precision == CF_MIXED) {
+    if (opt.fp64_kx < 1 || opt.fp64_kz < 1) return fail(CF_ERR_ARG, "fp64_kx and fp64_kz must be >= 1");
+    if (opt.refine_passes < 0 || opt.refine_passes > 8) return fail(CF_ERR_ARG, "refine_passes must be in [0, 8]");
+  }
+  if (opt.drop_tol < 0) opt.drop_tol = (opt.precision == CF_MIXED) ? 1e-7 : 1e-15;
+
+  cf_plan* pl = new cf_plan();
+  pl->nx = nx;
+  pl->ny = ny;
+  pl->nz = nz;
+  pl->nh = nx / 2;
+  pl->nkx = nx / 2 + 1;
+  pl->lx = lx;
+  pl->lz = lz;
+  pl->dx = lx / nx;
+  pl->dz = lz / nz;
+  pl->opt = opt;
+  pl->P = P;
+  pl->M = ny / P;
+  pl->yf.assign(y_faces, y_faces + ny + 1);
+  pl->dy.resize(ny);
+  for (int j = 0; j < ny; ++j) pl->dy[j] = pl->yf[j + 1] - pl->yf[j];
+  std::vector<double> yc(ny);
+  for (int j = 0; j < ny; ++j) yc[j] = 0.5 * (pl->yf[j] + pl->yf[j + 1]);
+  pl->dyc.resize(ny - 1);
+  for (int j = 0; j + 1 < ny; ++j) pl->dyc[j] = yc[j + 1] - yc[j];
+  // wall-normal rows of L_h = D o G (no flux through the walls)
+  pl->a.assign(ny, 0.0);
+  pl->c.assign(ny, 0.0);
+  for (int j = 1; j < ny; ++j) pl->a[j] = 1.0 / (pl->dy[j] * pl->dyc[j - 1]);
+  for (int j = 0; j + 1 < ny; ++j) pl->c[j] = 1.0 / (pl->dy[j] * pl->dyc[j]);
+  // modified wavenumbers: -(2 sin(pi k/n)/d)^2 are the eigenvalues of the periodic second difference
+  pl->kx2.resize(pl->nkx);
+  pl->kz2.resize(nz);
+  for (int k = 0; k < pl->nkx; ++k) {
+    const double sn = std::sin(M_PI * (double)k / (double)nx);
+    pl->kx2[k] = (2.0 * sn / pl->dx) * (2.0 * sn / pl->dx);
+  }
+  for (int k = 0; k < nz; ++k) {
+    const double sn = std::sin(M_PI * (double)k / (double)nz);
+    pl->kz2[k] = (2.0 * sn / pl->dz) * (2.0 * sn / pl->dz);
+  }
+  // drop threshold: smallest k^2 whose corner terms are all <= drop_tol
+  // (the corner terms fall monotonically with k^2)
+  {
+    double kmax = 0.0;
+    for (double v : pl->kx2) kmax = std::max(kmax, v);
+    double kzm = 0.0;
+    for (double v : pl->kz2) kzm = std::max(kzm, v);
+    kmax += kzm;
+    if (P <= 2) {
+      pl->k2drop = 0.0;
+    } else if (corner_delta(pl, kmax) > opt.drop_tol) {
+      pl->k2drop = INFINITY;
+    } else {
+      double lo = 0.0, hi = kmax;
+      if (corner_delta(pl, 0.0) <= opt.drop_tol) hi = 0.0;
+      for (int it = 0; it < 200 && hi > 0.0 && (hi - lo) > 1e-12 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (corner_delta(pl, mid) <= opt.drop_tol) hi = mid; else lo = mid;
+      }
+      pl->k2drop = hi;
+    }
+  }
+  // special lines: kx = kz = 0 always; the FP64 low set in mixed precision
+  pl->special.push_back(0);
+  if (opt.precision == CF_MIXED) {
+    for (int kx = 0; kx < std::min(opt.fp64_kx, pl->nkx); ++kx)
+      for (int kz = 0; kz < nz; ++kz) {
+        const int kzs = std::min(kz, nz - kz);
+        if ((kx == 0 && kz == 0) || kzs >= opt.fp64_kz) continue;
+        pl->special.push_back(kx * nz + kz);
+      }
+  }
+  pl->n_drop = 0;
+  for (int kx = 0; kx < pl->nkx; ++kx)
+    for (int kz = 0; kz < nz; ++kz)
+      if (pl->kx2[kx] + pl->kz2[kz] >= pl->k2drop) ++pl->n_drop;
+
+  // device side
+  hipError_t e = hipGetDevice(&pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return dev_fail(e, "hipGetDevice");
+  }
+  int lds_max = 0;
+  e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return dev_fail(e, "hipDeviceGetAttribute");
+  }
+  const size_t lds_need = cf::ysolve_lds_needed(ny, P, opt.precision == CF_FP64);
+  if (lds_need > (size_t)lds_max) {
+    delete pl;
+    return fail(CF_ERR_UNSUPPORTED, "partitioning needs " + std::to_string(lds_need) + " bytes of LDS per block");
+  }
+  auto bail = [&](cf_status s) {
+    free_all(pl);
+    delete pl;
+    return s;
+  };
+  std::vector<double> rdy(ny);
+  for (int j = 0; j < ny; ++j) rdy[j] = 1.0 / pl->dy[j];
+  cf_status st;
+  if ((st = upload(pl, &pl->d_a, pl->a)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_c, pl->c)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_dy, pl->dy)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_rdy, rdy)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_kx2, pl->kx2)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_kz2, pl->kz2)) != CF_OK) return bail(st);
+  auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+  if ((st = upload(pl, &pl->s_a, tof(pl->a))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->s_c, tof(pl->c))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->s_kx2, tof(pl->kx2))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->s_kz2, tof(pl->kz2))) != CF_OK) return bail(st);
+  std::vector<cx<double>> twz(nz), twx(pl->nh), twp(pl->nh + 1);
+  for (int m = 0; m < nz; ++m) twz[m] = unit_root(m, nz);
+  for (int m = 0; m < pl->nh; ++m) twx[m] = unit_root(m, pl->nh);
+  for (int m = 0; m <= pl->nh; ++m) twp[m] = unit_root(m, nx);
+  auto tofc = [](const std::vector<cx<double>>& v) {
+    std::vector<cx<float>> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = cf::mk((float)v[i].re, (float)v[i].im);
+    return o;
+  };
+  if ((st = upload(pl, &pl->tw_z64, twz)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->tw_x64, twx)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->twp64, twp)) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->tw_z32, tofc(twz))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->tw_x32, tofc(twx))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->twp32, tofc(twp))) != CF_OK) return bail(st);
+  if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
+  if ((st = dalloc(pl, &pl->d_special_scratch, pl->special.size() * 3 * (size_t)ny)) != CF_OK) return bail(st);
+  const size_t nspec = (size_t)ny * pl->nkx * nz;
+  if (opt.precision == CF_FP64) {
+    cx<double>* sp = nullptr;
+    if ((st = dalloc(pl, &sp, nspec)) != CF_OK) return bail(st);
+    pl->spec = sp;
+  } else {
+    cx<float>* sp = nullptr;
+    if ((st = dalloc(pl, &sp, nspec)) != CF_OK) return bail(st);
+    pl->spec = sp;
+  }
+  *out = pl;
+  return CF_OK;
+}
+
+void cf_plan_destroy(cf_plan* plan) {
+  if (!plan) return;
+  free_all(plan);
+  delete plan;
+}
+
+cf_status cf_plan_query(const cf_plan* pl, cf_plan_info* info) {
+  CF_TRY(check_plan(pl));
+  if (!info) return fail(CF_ERR_ARG, "info is NULL");
+  info->nx = pl->nx;
+  info->ny = pl->ny;
+  info->nz = pl->nz;
+  info->precision = pl->opt.precision;
+  info->n_parts = pl->P;
+  info->rows_per_part = pl->M;
+  info->n_lines = (long long)pl->nkx * pl->nz;
+  info->n_drop_lines = pl->n_drop;
+  info->n_special = (long long)pl->special.size();
+  info->k2_threshold = pl->k2drop;
+  info->workspace_bytes = pl->bytes;
+  return CF_OK;
+}
+
+cf_status cf_forward_spectral(cf_plan* pl, const double* f, void* fhat, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(f, "f"));
+  CF_TRY(check_ptr(fhat, "fhat"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed()) return forward_t<float>(pl, f, static_cast<cx<float>*>(fhat), s);
+  return forward_t<double>(pl, f, static_cast<cx<double>*>(fhat), s);
+}
+
+cf_status cf_inverse_spectral(cf_plan* pl, void* phat, double* p, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(phat, "phat"));
+  CF_TRY(check_ptr(p, "p"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed()) return inverse_t<float>(pl, static_cast<cx<float>*>(phat), p, s);
+  return inverse_t<double>(pl, static_cast<cx<double>*>(phat), p, s);
+}
+
+cf_status cf_solve_spectral(cf_plan* pl, const void* fhat, void* phat, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(fhat, "fhat"));
+  CF_TRY(check_ptr(phat, "phat"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed())
+    return solve_t<float>(pl, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), s);
+  return solve_t<double>(pl, static_cast<const cx<double>*>(fhat), static_cast<cx<double>*>(phat), s);
+}
+
+cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(f, "f"));
+  CF_TRY(check_ptr(p, "p"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed()) return poisson_t<float>(pl, f, p, s);
+  return poisson_t<double>(pl, f, p, s);
+}
+
+cf_status cf_divergence(cf_plan* pl, const double* u, const double* v, const double* w, double* f,
+                        double scale, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(u, "u"));
+  CF_TRY(check_ptr(v, "v"));
+  CF_TRY(check_ptr(w, "w"));
+  CF_TRY(check_ptr(f, "f"));
+  if (!std::isfinite(scale)) return fail(CF_ERR_ARG, "scale must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return timed(pl, CF_K_DIVERGENCE, s, "divergence launch", [&] {
+    return cf::launch_divergence(u, v, w, f, pl->d_rdy, 1.0 / pl->dx, 1.0 / pl->dz, scale, pl->nx, pl->ny,
+                                 pl->nz, s);
+  });
+}
+
+cf_status cf_plan_set_timing(cf_plan* pl, int enable) {
+  CF_TRY(check_plan(pl));
+  if (!enable) CF_TRY(harvest(pl));
+  pl->timing = enable != 0;
+  return CF_OK;
+}
+
+cf_status cf_plan_reset_timing(cf_plan* pl) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(harvest(pl));
+  for (int k = 0; k < CF_K_COUNT; ++k) {
+    pl->acc_ms[k] = 0.0;
+    pl->acc_n[k] = 0;
+  }
+  return CF_OK;
+}
+
+cf_status cf_plan_get_timing(cf_plan* pl, int kernel, double* total_ms, long long* launches) {
+  CF_TRY(check_plan(pl));
+  if (kernel < 0 || kernel >= CF_K_COUNT) return fail(CF_ERR_ARG, "kernel class out of range");
+  if (!total_ms || !launches) return fail(CF_ERR_ARG, "output pointer is NULL");
+  CF_TRY(harvest(pl));
+  *total_ms = pl->acc_ms[kernel];
+  *launches = pl->acc_n[kernel];
+  return CF_OK;
+}
+
+const char* cf_kernel_name(int k) {
+  static const char* names[CF_K_COUNT] = {"r2c_x", "fft_z_fwd", "ysolve", "special_lines",
+                                          "fft_z_inv", "c2r_x", "divergence"};
+  return (k >= 0 && k < CF_K_COUNT) ? names[k] : "unknown";
+}
+
+}  // extern "C"

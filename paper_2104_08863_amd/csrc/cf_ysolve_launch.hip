@@ -1,0 +1,87 @@
+// Launch of the wall-normal line solves.
+#include "cf_internal.h"
+#include "cf_ysolve_kernels.h"
+
+namespace cf {
+
+#define CF_FOR_EACH_M(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
+
+bool ysolve_m_compiled(int m) {
+  switch (m) {
+#define CF_CASE(M) case M:
+    CF_FOR_EACH_M(CF_CASE)
+#undef CF_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+// Lines per block: at least 16 consecutive lines per row access where the
+// block stays within 512 threads, about 256 threads per block otherwise.
+static int lines_per_block(int P) {
+  int lb = 256 / P;
+  if (lb < 16) lb = 16;
+  while (lb * P > 512) lb /= 2;
+  return lb;
+}
+
+template <typename T>
+hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,
+                         const T* kx2, const T* kz2, T k2drop, hipStream_t s) {
+  YArgs ya;
+  ya.ny = y.ny;
+  ya.nz = y.nz;
+  ya.nkx = y.nkx;
+  ya.P = y.P;
+  ya.LB = lines_per_block(y.P);
+  ya.nlines = y.nlines;
+  ya.skip_kx = y.skip_kx;
+  ya.skip_kz = y.skip_kz;
+  const long blocks = (y.nlines + ya.LB - 1) / ya.LB;
+  const size_t lds = ysolve_lds_bytes<T>(y.ny, y.P, ya.LB);
+  const dim3 threads(ya.LB * y.P);
+  switch (y.M) {
+#define CF_CASE(M)                                                                                   \
+  case M:                                                                                           \
+    hipLaunchKernelGGL((k_ysolve<T, M>), dim3(blocks), threads, lds, s, fin, pout, a, c, kx2, kz2, \
+                       k2drop, ya);                                                                 \
+    return hipGetLastError();
+    CF_FOR_EACH_M(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+// Dynamic LDS needed by a y-solve launch (checked by the plan against the
+// device limit).
+size_t ysolve_lds_needed(int ny, int P, bool fp64) {
+  const int lb = lines_per_block(P);
+  return fp64 ? ysolve_lds_bytes<double>(ny, P, lb) : ysolve_lds_bytes<float>(ny, P, lb);
+}
+
+template <typename T>
+hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* c,
+                                const double* dy, const double* kx2, const double* kz2,
+                                const int* lines, int n_lines, double* scratch, int ny, int nz,
+                                int nkx, hipStream_t s) {
+  if (n_lines <= 0) return hipSuccess;
+  const int th = 64;
+  const int blocks = (n_lines + th - 1) / th;
+  hipLaunchKernelGGL((k_special_lines<T>), dim3(blocks), dim3(th), 0, s, fin, pout, a, c, dy, kx2, kz2,
+                     lines, n_lines, scratch, ny, nz, nkx);
+  return hipGetLastError();
+}
+
+#define CF_INST(T)                                                                                  \
+  template hipError_t launch_ysolve<T>(const YLaunch&, const cx<T>*, cx<T>*, const T*, const T*,   \
+                                       const T*, const T*, T, hipStream_t);                        \
+  template hipError_t launch_special_lines<T>(const cx<T>*, cx<T>*, const double*, const double*, \
+                                              const double*, const double*, const double*,        \
+                                              const int*, int, double*, int, int, int, hipStream_t);
+CF_INST(double)
+CF_INST(float)
+#undef CF_INST
+
+}  // namespace cf

@@ -1,0 +1,146 @@
+"""GPU parity of the Poisson path (HIP kernels through the C ABI) against the
+FP64 oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, nz, gamma, n_parts): config sizes, several tiles, ragged tails,
+# radix-3 lengths and non-power-of-two partition counts
+CASES = [
+    (64, 64, 64, 2.0, 0),
+    (64, 64, 64, 2.0, 4),
+    (48, 24, 12, 2.0, 0),
+    (96, 36, 24, 2.5, 3),
+    (16, 8, 6, 1.0, 0),
+    (128, 128, 96, 2.0, 8),
+    (256, 96, 48, 2.5, 6),
+    (32, 16, 2, 2.0, 1),
+]
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def plan_for(nx, ny, nz, gamma, n_parts=0, precision="fp64", lx=2 * np.pi, lz=np.pi, **kw):
+    from paper_2104_08863_amd.api import Plan
+    yf = synth.tanh_faces(ny, gamma)
+    return Plan(nx, ny, nz, lx, lz, yf, precision=precision, n_parts=n_parts, **kw), \
+        O.Box(nx, ny, nz, lx, lz, yf)
+
+
+def rel(a, b):
+    return (np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
+def test_forward_and_inverse_transforms(nx, ny, nz, gamma, parts):
+    pl, box = plan_for(nx, ny, nz, gamma, parts)
+    f = synth.uniform_rhs(nx, ny, nz, seed=1)
+    fg = torch.tensor(f, device=dev())
+    fh = pl.forward_spectral(fg)
+    ref = O.forward_transform(torch.tensor(f)).permute(0, 2, 1).numpy()   # (ny, nkx, nz)
+    got = fh.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    back = pl.inverse_spectral(fh).cpu().numpy()
+    assert np.abs(back - f).max() <= 1e-14 * max(1.0, np.log2(nx * nz))
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
+def test_solve_spectral_per_mode(nx, ny, nz, gamma, parts):
+    pl, box = plan_for(nx, ny, nz, gamma, parts)
+    rng = np.random.default_rng(2)
+    fh = rng.standard_normal((ny, nx // 2 + 1, nz)) + 1j * rng.standard_normal((ny, nx // 2 + 1, nz))
+    fh[:, 0, 0].imag = 0.0
+    fg = torch.tensor(fh, device=dev())
+    ph = pl.solve_spectral(fg).cpu().numpy()
+    ref = O.solve_spectral(torch.tensor(fh).permute(0, 2, 1), box).permute(0, 2, 1).numpy()
+    err = np.abs(ph - ref).max(axis=0) / np.abs(ref).max(axis=0)      # per (kx, kz) line
+    assert err.max() <= 1e-11, f"worst line {np.unravel_index(err.argmax(), err.shape)}: {err.max():.3e}"
+    # in place
+    ph2 = pl.solve_spectral(fg, out=fg).cpu().numpy()
+    assert np.array_equal(ph2, ph)
+
+
+def test_drop_path_matches_oracle_pdd():
+    """A plan with few partitions and a loose tolerance drops the corner terms
+    on the high-wavenumber lines; those lines follow the oracle's dropped PDD."""
+    nx, ny, nz = 64, 64, 64
+    pl, box = plan_for(nx, ny, nz, 2.0, n_parts=4, drop_tol=1e-9)
+    info = pl.info()
+    assert 0 < info["n_drop_lines"] < info["n_lines"]
+    rng = np.random.default_rng(4)
+    fh = rng.standard_normal((ny, nx // 2 + 1, nz)) + 1j * rng.standard_normal((ny, nx // 2 + 1, nz))
+    ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy()
+    a, c, k2 = O.line_coefficients(box)
+    k2 = k2.numpy().T                                                    # (nkx, nz)
+    exact = O.solve_spectral(torch.tensor(fh).permute(0, 2, 1), box).permute(0, 2, 1).numpy()
+    drop_lines = np.argwhere(k2 >= info["k2_threshold"])
+    sel = drop_lines[:: max(1, len(drop_lines) // 200)]
+    b = -(a + c)[:, None] - torch.tensor(k2[sel[:, 0], sel[:, 1]])[None, :]
+    d = torch.tensor(fh[:, sel[:, 0], sel[:, 1]])
+    ref = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
+    got = ph[:, sel[:, 0], sel[:, 1]]
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+    ex = exact[:, sel[:, 0], sel[:, 1]]
+    assert (np.abs(got - ex).max(0) / np.abs(ex).max(0)).max() <= 1e-8
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
+def test_poisson_solve_matches_oracle(nx, ny, nz, gamma, parts):
+    pl, box = plan_for(nx, ny, nz, gamma, parts)
+    u, v, w = synth.uniform_velocity(nx, ny, nz, seed=0)
+    ug, vg, wg = (torch.tensor(q, device=dev()) for q in (u, v, w))
+    fg = pl.divergence(ug, vg, wg)
+    f_ref = O.divergence(*(torch.tensor(q) for q in (u, v, w)), box)
+    assert (fg.cpu() - f_ref).abs().max() <= 1e-12 * f_ref.abs().max()
+    pg = pl.poisson_solve(fg).cpu().numpy()
+    p_ref = O.poisson(f_ref, box).numpy()
+    assert rel(pg, p_ref) <= 1e-12
+    # aliasing p = f is allowed
+    pg2 = pl.poisson_solve(fg, out=fg).cpu().numpy()
+    assert np.array_equal(pg2, pg)
+
+
+def test_poisson_64cubed_config_and_determinism():
+    wl = synth.WORKLOADS["poisson64"]
+    pl, box = plan_for(wl.nx, wl.ny, wl.nz, wl.gamma, lx=wl.lx, lz=wl.lz)
+    f = synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0)
+    fg = torch.tensor(f, device=dev())
+    p1 = pl.poisson_solve(fg)
+    p2 = pl.poisson_solve(fg)
+    assert torch.equal(p1, p2)
+    p_ref = O.poisson(torch.tensor(f), box).numpy()
+    assert rel(p1.cpu().numpy(), p_ref) <= 1e-12
+    # gauge and residual
+    pc = torch.tensor(p1.cpu().numpy())
+    assert abs(O.mean_w(pc, box).item()) < 1e-14
+    r = O.laplacian_p(pc, box) - (torch.tensor(f) - O.mean_w(torch.tensor(f), box))
+    assert r.abs().max() <= 1e-10 * torch.tensor(f).abs().max()
+
+
+def test_empty_stream_and_plan_reuse():
+    """Two plans live at once and alternate on the same stream."""
+    pa, ba = plan_for(32, 16, 8, 2.0)
+    pb, bb = plan_for(64, 32, 24, 2.5)
+    for _ in range(2):
+        for pl, box in ((pa, ba), (pb, bb)):
+            f = synth.uniform_rhs(box.nx, box.ny, box.nz, seed=5)
+            p = pl.poisson_solve(torch.tensor(f, device=dev())).cpu().numpy()
+            assert rel(p, O.poisson(torch.tensor(f), box).numpy()) <= 1e-12
+
+
+def test_bad_tensor_arguments_rejected():
+    pl, box = plan_for(32, 16, 8, 2.0)
+    f = torch.zeros(16, 8, 32, dtype=torch.float64, device=dev())
+    with pytest.raises(TypeError):
+        pl.poisson_solve(f.float())
+    with pytest.raises(ValueError):
+        pl.poisson_solve(f[:, :, :16])
+    with pytest.raises(ValueError):
+        pl.poisson_solve(f.transpose(1, 2).contiguous().transpose(1, 2))
