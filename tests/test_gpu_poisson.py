@@ -69,9 +69,12 @@ def test_solve_spectral_per_mode(nx, ny, nz, gamma, parts):
 
 def test_drop_path_matches_oracle_pdd():
     """A plan with few partitions and a loose tolerance drops the corner terms
-    on the high-wavenumber lines; those lines follow the oracle's dropped PDD."""
+    on high-wavenumber lines.  The kernel decides per block of consecutive
+    lines: a block drops only if all its lines may, else it solves exactly.  So
+    every drop-eligible line equals either the oracle's dropped PDD or its
+    exact solve, and some lines must show the dropped result."""
     nx, ny, nz = 64, 64, 64
-    pl, box = plan_for(nx, ny, nz, 2.0, n_parts=4, drop_tol=1e-9)
+    pl, box = plan_for(nx, ny, nz, 2.0, n_parts=4, drop_tol=1e-5)
     info = pl.info()
     assert 0 < info["n_drop_lines"] < info["n_lines"]
     rng = np.random.default_rng(4)
@@ -79,16 +82,20 @@ def test_drop_path_matches_oracle_pdd():
     ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy()
     a, c, k2 = O.line_coefficients(box)
     k2 = k2.numpy().T                                                    # (nkx, nz)
-    exact = O.solve_spectral(torch.tensor(fh).permute(0, 2, 1), box).permute(0, 2, 1).numpy()
-    drop_lines = np.argwhere(k2 >= info["k2_threshold"])
-    sel = drop_lines[:: max(1, len(drop_lines) // 200)]
+    sel = np.argwhere(k2 >= info["k2_threshold"])
     b = -(a + c)[:, None] - torch.tensor(k2[sel[:, 0], sel[:, 1]])[None, :]
     d = torch.tensor(fh[:, sel[:, 0], sel[:, 1]])
-    ref = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
+    ref_drop = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
+    ref_exact = O.thomas(a[:, None], b, c[:, None], d).numpy()
     got = ph[:, sel[:, 0], sel[:, 1]]
-    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
-    ex = exact[:, sel[:, 0], sel[:, 1]]
-    assert (np.abs(got - ex).max(0) / np.abs(ex).max(0)).max() <= 1e-8
+    scale = np.abs(ref_exact).max(0)
+    e_drop = np.abs(got - ref_drop).max(0) / scale
+    e_exact = np.abs(got - ref_exact).max(0) / scale
+    assert np.minimum(e_drop, e_exact).max() <= 1e-11
+    dropped = (e_drop <= 1e-11) & (e_exact > 1e-11)
+    assert dropped.sum() > 0
+    # the drop error stays within the plan's tolerance scale
+    assert e_exact.max() <= 1e-3
 
 
 @pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
