@@ -18,7 +18,8 @@
  *                                                 on input and written as 0)
  *   w[j][k][i]  at (x_i,       yc_j,        z_{k+1/2})
  * Spectral arrays (test hooks only) are complex (re, im interleaved) of shape
- * (ny, nx/2+1, nz), z fastest, holding the unnormalised forward transform.
+ * (nx/2+1, ny, nz), z fastest, holding the unnormalised forward transform: the
+ * wall-normal line of wavenumbers (kx, kz) is fhat[kx][:][kz].
  *
  * Conventions for every call:
  *   - Pointers to fields are DEVICE pointers on the plan's device, 16-byte
@@ -118,12 +119,12 @@ cf_status cf_divergence(cf_plan* plan, const double* u, const double* v, const d
 
 /* Test hook, steps (2)-(4): forward real transform in x then complex transform in z of f
  * (device double (ny, nz, nx)) into fhat (device complex, plan precision: double pairs
- * for CF_FP64, float pairs for CF_MIXED; shape (ny, nx/2+1, nz)). */
+ * for CF_FP64, float pairs for CF_MIXED; shape (nx/2+1, ny, nz)). */
 cf_status cf_forward_spectral(cf_plan* plan, const double* f, void* fhat, void* stream);
 
 /* Test hook, steps (6)-(8): inverse transforms of phat (layout as above) into p, scaled
- * by 1/(nx nz).  phat is overwritten. */
-cf_status cf_inverse_spectral(cf_plan* plan, void* phat, double* p, void* stream);
+ * by 1/(nx nz).  phat is not modified. */
+cf_status cf_inverse_spectral(cf_plan* plan, const void* phat, double* p, void* stream);
 
 /* Test hook, step (5): solve every wall-normal line of fhat (Eq. (9) with the PDD of
  * Section 2.2, exact or dropped reduced system per the plan, gauge on the kx=kz=0 line)

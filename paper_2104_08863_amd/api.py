@@ -93,7 +93,7 @@ class Plan:
 
     @property
     def spec_shape(self):
-        return (self.ny, self.nkx, self.nz)
+        return (self.nkx, self.ny, self.nz)
 
     def _field(self, t: torch.Tensor, name: str, dtype=torch.float64):
         if not isinstance(t, torch.Tensor):
@@ -143,7 +143,7 @@ class Plan:
         return out
 
     def inverse_spectral(self, fhat: torch.Tensor, out=None) -> torch.Tensor:
-        """Inverse transforms; fhat is overwritten."""
+        """Inverse transforms of a spectrum of shape (nx/2+1, ny, nz)."""
         self._spec(fhat, "fhat")
         out = self._new() if out is None else self._field(out, "out")
         L.check(L.lib().cf_inverse_spectral(self._h, _ptr(fhat), _ptr(out), _stream()), "cf_inverse_spectral")

@@ -39,6 +39,29 @@ template <bool INV, typename T> CF_HD cx<T> mul_mi(cx<T> a) {
   return INV ? mk(-a.im, a.re) : mk(a.im, -a.re);
 }
 
+// Reciprocal: on the device the hardware estimate refined by Newton steps
+// (error about one ulp, no IEEE division sequence); on the host 1/x.
+CF_HD double rcp(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+CF_HD float rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = __builtin_fmaf(-x, r, 1.0f);
+  return __builtin_fmaf(r, e, r);
+#else
+  return 1.0f / x;
+#endif
+}
+
 template <typename T> CF_HD T cf_max(T a, T b) { return a > b ? a : b; }
 template <typename T> CF_HD T cf_min(T a, T b) { return a < b ? a : b; }
 

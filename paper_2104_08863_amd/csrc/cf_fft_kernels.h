@@ -1,7 +1,12 @@
 // Batched LDS Stockham FFT kernels for the periodic directions.
 //
-// Spectral layout (owned by the plan): complex, [ny][nx/2+1][nz], z fastest.
-//   * k_fft_z     : complex transform of every contiguous z-line, in place.
+// Two spectral layouts, both with z fastest (every z-line contiguous):
+//   A = [ny][nx/2+1][nz]  (x-side: the real transforms read and write it)
+//   B = [nx/2+1][ny][nz]  (y-side: a wall-normal line is a column of one
+//                          contiguous kx-slab)
+//   * k_fft_z     : complex transform of every z-line, moving it from one
+//                   layout to the other (line (o, i) of an [no][ni] array of
+//                   lines goes to line (i, o)).
 //   * k_r2c_x     : real transform of K consecutive x-rows (fixed j, rows
 //                   k0..k0+K-1) through a half-length complex transform,
 //                   written transposed into the spectral layout (for every kx
@@ -74,15 +79,19 @@ struct ZCfg {
 
 template <typename T, int N, bool INV>
 __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
-k_fft_z(cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, long nlines) {
+k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __restrict__ tw, int no,
+        int ni) {
   using F = FftT<N>;
   constexpr int LPB = ZCfg<T, N>::LPB;
   __shared__ cx<T> lds[LPB * N];
   const int tl = threadIdx.x % F::TPL;
   const int lb = threadIdx.x / F::TPL;
+  const long nlines = (long)no * ni;
   const long line = (long)blockIdx.x * LPB + lb;
   const bool ok = line < nlines;
-  cx<T>* g = data + (ok ? line : 0) * N;
+  const long lo = ok ? line : 0;
+  const cx<T>* g = src + lo * N;
+  cx<T>* o = dst + ((lo % ni) * no + lo / ni) * N;
   cx<T> x[F::E];
 #pragma unroll
   for (int q = 0; q < F::E / F::R0; ++q) {
@@ -96,7 +105,7 @@ k_fft_z(cx<T>* __restrict__ data, const cx<T>* __restrict__ tw, long nlines) {
     for (int q = 0; q < F::E / F::RL; ++q) {
       const int b = tl + q * F::TPL;
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) g[b + r * (N / F::RL)] = x[q * F::RL + r];
+      for (int r = 0; r < F::RL; ++r) o[b + r * (N / F::RL)] = x[q * F::RL + r];
     }
   }
 }
@@ -161,10 +170,14 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const c
   }
   __syncthreads();
   const long plane = (long)j * NKX;
-  for (int idx = threadIdx.x; idx < NKX * K; idx += blockDim.x) {
+  constexpr int TH = XCfg<T, NH>::THREADS;
+  constexpr int ITEMS = NKX * K;
+#pragma unroll
+  for (int it = 0; it < (ITEMS + TH - 1) / TH; ++it) {
+    const int idx = threadIdx.x + it * TH;
     const int r = idx % K;
     const int kx = idx / K;
-    if (k0 + r < nz) {
+    if (idx < ITEMS && k0 + r < nz) {
       const cx<T>* row = lds + r * S;
       cx<T> X = r2c_post(row[kx == NH ? 0 : kx], row[kx == 0 ? 0 : NH - kx], twp[kx]);
       spec[(plane + kx) * nz + k0 + r] = X;
@@ -197,10 +210,23 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* __restrict__ tw,
   const int j = blockIdx.x / nzb;
   const int k0 = (blockIdx.x % nzb) * K;
   const long plane = (long)j * NKX;
-  for (int idx = threadIdx.x; idx < NKX * K; idx += blockDim.x) {
-    const int r = idx % K;
-    const int kx = idx / K;
-    lds[r * S + kx] = (k0 + r < nz) ? spec[(plane + kx) * nz + k0 + r] : mk(T(0), T(0));
+  {
+    constexpr int TH = XCfg<T, NH>::THREADS;
+    constexpr int ITEMS = NKX * K;
+    constexpr int IT = (ITEMS + TH - 1) / TH;
+    cx<T> v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * TH;
+      const int r = idx % K;
+      const int kx = idx / K;
+      v[it] = (idx < ITEMS && k0 + r < nz) ? spec[(plane + kx) * nz + k0 + r] : mk(T(0), T(0));
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int idx = threadIdx.x + it * TH;
+      if (idx < ITEMS) lds[(idx % K) * S + idx / K] = v[it];
+    }
   }
   __syncthreads();
   const int tl = threadIdx.x % F::TPL;

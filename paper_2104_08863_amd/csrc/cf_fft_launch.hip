@@ -20,23 +20,25 @@ bool fft_len_compiled(int n) {
 }
 
 template <typename T, int N>
-static hipError_t fft_z_n(bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s) {
+static hipError_t fft_z_n(bool inv, const cx<T>* src, cx<T>* dst, const cx<T>* tw, int no, int ni,
+                          hipStream_t s) {
   using C = ZCfg<T, N>;
-  const long blocks = (nlines + C::LPB - 1) / C::LPB;
+  const long blocks = ((long)no * ni + C::LPB - 1) / C::LPB;
   if (blocks <= 0) return hipSuccess;
   if (inv)
-    hipLaunchKernelGGL((k_fft_z<T, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, data, tw, nlines);
+    hipLaunchKernelGGL((k_fft_z<T, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
   else
-    hipLaunchKernelGGL((k_fft_z<T, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, data, tw, nlines);
+    hipLaunchKernelGGL((k_fft_z<T, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_fft_z(int n, bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s) {
+hipError_t launch_fft_z(int n, bool inv, const cx<T>* src, cx<T>* dst, const cx<T>* tw, int no, int ni,
+                        hipStream_t s) {
   switch (n) {
 #define CF_CASE(N) \
   case N:          \
-    return fft_z_n<T, N>(inv, data, tw, nlines, s);
+    return fft_z_n<T, N>(inv, src, dst, tw, no, ni, s);
     CF_FOR_EACH_LEN(CF_CASE)
 #undef CF_CASE
     default:
@@ -97,7 +99,7 @@ hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* t
 }
 
 #define CF_INST(T)                                                                                   \
-  template hipError_t launch_fft_z<T>(int, bool, cx<T>*, const cx<T>*, long, hipStream_t);           \
+  template hipError_t launch_fft_z<T>(int, bool, const cx<T>*, cx<T>*, const cx<T>*, int, int, hipStream_t); \
   template hipError_t launch_r2c_plain<T>(int, const double*, cx<T>*, const cx<T>*, const cx<T>*, int, \
                                           int, hipStream_t);                                         \
   template hipError_t launch_c2r_plain<T>(int, const cx<T>*, double*, const cx<T>*, const cx<T>*, int, \

@@ -10,8 +10,11 @@ namespace cf {
 // Transform lengths with compiled kernels: 2^a and 3*2^a from 2 to 2048.
 bool fft_len_compiled(int n);
 
+// Complex transform of the no*ni z-lines of src (line (o, i) at (o*ni + i)*n),
+// written to line (i, o) of dst; src and dst must not overlap.
 template <typename T>
-hipError_t launch_fft_z(int n, bool inv, cx<T>* data, const cx<T>* tw, long nlines, hipStream_t s);
+hipError_t launch_fft_z(int n, bool inv, const cx<T>* src, cx<T>* dst, const cx<T>* tw, int no, int ni,
+                        hipStream_t s);
 
 // Forward real transform of rows of a plain array (Tin = double, stored as
 // (ny, nz, nx)) into the transposed spectrum.
@@ -39,11 +42,12 @@ template <typename T>
 hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,
                          const T* kx2, const T* kz2, T k2drop, hipStream_t s);
 
+// Whole-line FP64 Thomas on the listed lines of layout B, with per-line
+// elimination factors den, cp ([n_lines][ny]) prepared by the plan.
 template <typename T>
-hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* c,
-                                const double* dy, const double* kx2, const double* kz2,
-                                const int* lines, int n_lines, double* scratch, int ny, int nz,
-                                int nkx, hipStream_t s);
+hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* den,
+                                const double* cp, const double* dy, const int* lines, int n_lines,
+                                int ny, int nz, hipStream_t s);
 
 bool ysolve_m_compiled(int m);
 

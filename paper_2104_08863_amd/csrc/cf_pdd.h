@@ -35,7 +35,7 @@ template <typename T> CF_HD m22<T> m22_add(m22<T> x, m22<T> y) {
   return m22<T>{x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d};
 }
 template <typename T> CF_HD m22<T> m22_inv(m22<T> x) {
-  T r = T(1) / (x.a * x.d - x.b * x.c);
+  T r = rcp(x.a * x.d - x.b * x.c);
   return m22<T>{x.d * r, -x.b * r, -x.c * r, x.a * r};
 }
 template <typename T> CF_HD m22<T> m22_neg(m22<T> x) { return m22<T>{-x.a, -x.b, -x.c, -x.d}; }
@@ -52,6 +52,31 @@ struct zrow {
   cx<T> r0, r1;
 };
 
+// Structure-of-arrays storage of reduced-system rows (16 planes of n values),
+// so that neighbouring lanes touch neighbouring addresses.
+template <typename T>
+struct zrow_soa {
+  T* base;
+  int n;
+  CF_HD void put(int k, const zrow<T>& z) const {
+    T* p = base + k;
+    const T v[16] = {z.L.a, z.L.b, z.L.c, z.L.d, z.D.a, z.D.b, z.D.c, z.D.d,
+                     z.U.a, z.U.b, z.U.c, z.U.d, z.r0.re, z.r0.im, z.r1.re, z.r1.im};
+#pragma unroll
+    for (int f = 0; f < 16; ++f) p[f * n] = v[f];
+  }
+  CF_HD zrow<T> get(int k) const {
+    const T* p = base + k;
+    zrow<T> z;
+    z.L = m22<T>{p[0 * n], p[1 * n], p[2 * n], p[3 * n]};
+    z.D = m22<T>{p[4 * n], p[5 * n], p[6 * n], p[7 * n]};
+    z.U = m22<T>{p[8 * n], p[9 * n], p[10 * n], p[11 * n]};
+    z.r0 = mk(p[12 * n], p[13 * n]);
+    z.r1 = mk(p[14 * n], p[15 * n]);
+    return z;
+  }
+};
+
 // Local solves of one partition (Eq. (20)): arow[s] = a_{j0+s}, crow[s] =
 // c_{j0+s} (s = 0..M-1).  On entry d holds the right-hand side; on exit d
 // holds xt, and v, w the two spike columns.
@@ -65,7 +90,7 @@ CF_HD void pdd_local(const T* arow, const T* crow, T k2, cx<T>* d, T* v, T* w) {
     T bs = -(as + cs) - k2;
     T cin = (s == M - 1) ? T(0) : cs;
     T den = (s == 0) ? bs : bs - as * cp[s - 1];
-    T rden = T(1) / den;
+    T rden = rcp(den);
     cp[s] = cin * rden;
     if (s == 0) {
       d[0] = d[0] * rden;
@@ -88,7 +113,7 @@ CF_HD void pdd_local(const T* arow, const T* crow, T k2, cx<T>* d, T* v, T* w) {
 // Step 4 with the corner terms dropped: Cramer's rule on D_i.
 template <typename T>
 CF_HD void pdd_cramer(T wm, T v1n, cx<T> xm, cx<T> x1n, cx<T>& y1, cx<T>& y2) {
-  T rdet = T(1) / (T(1) - wm * v1n);
+  T rdet = rcp(T(1) - wm * v1n);
   y1 = (xm - x1n * wm) * rdet;
   y2 = (x1n - xm * v1n) * rdet;
 }

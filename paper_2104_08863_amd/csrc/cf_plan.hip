@@ -74,9 +74,16 @@ struct cf_plan {
   cx<double>*tw_z64 = nullptr, *tw_x64 = nullptr, *twp64 = nullptr;
   cx<float>*tw_z32 = nullptr, *tw_x32 = nullptr, *twp32 = nullptr;
   int* d_special = nullptr;
-  double* d_special_scratch = nullptr;
-  void* spec = nullptr;  // spectral workspace, (ny, nkx, nz) complex of the bulk precision
+  double* d_special_den = nullptr;  // [n_special][ny] elimination pivots
+  double* d_special_cp = nullptr;   // [n_special][ny] eliminated upper coefficients
+  // spectral workspaces of the bulk precision: layout A (ny, nkx, nz) on the
+  // x side, layout B (nkx, ny, nz) on the wall-normal side
+  void* specA = nullptr;
+  void* specB = nullptr;
   bool mixed() const { return opt.precision == CF_MIXED; }
+  // side stream for the whole-line solves, which overlap the PDD kernel
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // per-kernel event timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // created on demand, reused after each harvest
@@ -123,6 +130,11 @@ void free_all(cf_plan* pl) {
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
   pl->events.clear();
   pl->pending.clear();
+  if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+  if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+  if (pl->aux) (void)hipStreamDestroy(pl->aux);
+  pl->ev_fork = pl->ev_join = nullptr;
+  pl->aux = nullptr;
 }
 
 hipError_t next_event(cf_plan* pl, hipEvent_t* ev) {
@@ -256,27 +268,31 @@ struct Tabs<float> {
   static const cx<float>* twp(const cf_plan* p) { return p->twp32; }
 };
 
+// f (physical) -> spectrum in layout B
 template <typename T>
-cf_status forward_t(cf_plan* pl, const double* f, cx<T>* spec, hipStream_t s) {
+cf_status forward_t(cf_plan* pl, const double* f, cx<T>* outB, hipStream_t s) {
   using TB = Tabs<T>;
+  cx<T>* A = static_cast<cx<T>*>(pl->specA);
   CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c launch", [&] {
-    return cf::launch_r2c_plain<T>(pl->nh, f, spec, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+    return cf::launch_r2c_plain<T>(pl->nh, f, A, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
   }));
   CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
-    return cf::launch_fft_z<T>(pl->nz, false, spec, TB::twz(pl), (long)pl->ny * pl->nkx, s);
+    return cf::launch_fft_z<T>(pl->nz, false, A, outB, TB::twz(pl), pl->ny, pl->nkx, s);
   }));
   return CF_OK;
 }
 
+// spectrum in layout B -> p (physical), scaled by 1/(nx nz); inB is not modified
 template <typename T>
-cf_status inverse_t(cf_plan* pl, cx<T>* spec, double* p, hipStream_t s) {
+cf_status inverse_t(cf_plan* pl, const cx<T>* inB, double* p, hipStream_t s) {
   using TB = Tabs<T>;
+  cx<T>* A = static_cast<cx<T>*>(pl->specA);
   CF_TRY(timed(pl, CF_K_FFT_Z_INV, s, "z ifft launch", [&] {
-    return cf::launch_fft_z<T>(pl->nz, true, spec, TB::twz(pl), (long)pl->ny * pl->nkx, s);
+    return cf::launch_fft_z<T>(pl->nz, true, inB, A, TB::twz(pl), pl->nkx, pl->ny, s);
   }));
   const T scale = T(1.0 / ((double)pl->nx * (double)pl->nz));
   CF_TRY(timed(pl, CF_K_C2R_X, s, "c2r launch", [&] {
-    return cf::launch_c2r_plain<T>(pl->nh, spec, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scale, s);
+    return cf::launch_c2r_plain<T>(pl->nh, A, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scale, s);
   }));
   return CF_OK;
 }
@@ -294,24 +310,57 @@ cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
   y.skip_kx = pl->mixed() ? pl->opt.fp64_kx : 0;
   y.skip_kz = pl->mixed() ? pl->opt.fp64_kz : 0;
   const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
+  // The whole-line solves run on the side stream next to the PDD kernel: they
+  // read and write only the special lines, which the PDD kernel reads but does
+  // not write (lines are independent there, so the values it reads for them
+  // are discarded).
+  CF_HIP(hipEventRecord(pl->ev_fork, s), "hipEventRecord");
+  CF_HIP(hipStreamWaitEvent(pl->aux, pl->ev_fork, 0), "hipStreamWaitEvent");
+  CF_TRY(timed(pl, CF_K_SPECIAL, pl->aux, "special-line launch", [&] {
+    return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_special_den, pl->d_special_cp, pl->d_dy,
+                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, pl->aux);
+  }));
+  CF_HIP(hipEventRecord(pl->ev_join, pl->aux), "hipEventRecord");
   CF_TRY(timed(pl, CF_K_YSOLVE, s, "y-solve launch", [&] {
     return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
   }));
-  CF_TRY(timed(pl, CF_K_SPECIAL, s, "special-line launch", [&] {
-    return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_c, pl->d_dy, pl->d_kx2, pl->d_kz2,
-                                       pl->d_special, (int)pl->special.size(), pl->d_special_scratch,
-                                       pl->ny, pl->nz, pl->nkx, s);
-  }));
+  CF_HIP(hipStreamWaitEvent(s, pl->ev_join, 0), "hipStreamWaitEvent");
   return CF_OK;
 }
 
 template <typename T>
 cf_status poisson_t(cf_plan* pl, const double* f, double* p, hipStream_t s) {
-  cx<T>* spec = static_cast<cx<T>*>(pl->spec);
-  CF_TRY(forward_t<T>(pl, f, spec, s));
-  CF_TRY(solve_t<T>(pl, spec, spec, s));
-  CF_TRY(inverse_t<T>(pl, spec, p, s));
+  cx<T>* B = static_cast<cx<T>*>(pl->specB);
+  CF_TRY(forward_t<T>(pl, f, B, s));
+  CF_TRY(solve_t<T>(pl, B, B, s));
+  CF_TRY(inverse_t<T>(pl, B, p, s));
   return CF_OK;
+}
+
+// Elimination factors of one whole-line solve, in the operation order of the
+// textbook Thomas algorithm (no contraction).
+void special_factors(const cf_plan* pl, int line, double* den, double* cp) {
+#pragma clang fp contract(off)
+  const int ny = pl->ny, nz = pl->nz;
+  const int kx = line / nz, kz = line % nz;
+  const double k2 = pl->kx2[kx] + pl->kz2[kz];
+  const bool mean_line = (line == 0);
+  const int n = mean_line ? ny - 1 : ny;
+  double cprev = 0.0;
+  for (int j = 0; j < ny; ++j) {
+    if (j >= n) {
+      den[j] = 1.0;
+      cp[j] = 0.0;
+      continue;
+    }
+    const double b = -(pl->a[j] + pl->c[j]) - k2;
+    const double t = pl->a[j] * cprev;
+    const double d = (j == 0) ? b : b - t;
+    const double cj = (j == n - 1) ? 0.0 : pl->c[j];
+    den[j] = d;
+    cp[j] = cj / d;
+    cprev = cp[j];
+  }
 }
 
 }  // namespace
@@ -471,6 +520,10 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   std::vector<double> rdy(ny);
   for (int j = 0; j < ny; ++j) rdy[j] = 1.0 / pl->dy[j];
   cf_status st;
+  e = hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) return bail(dev_fail(e, "stream/event creation"));
   if ((st = upload(pl, &pl->d_a, pl->a)) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->d_c, pl->c)) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->d_dy, pl->dy)) != CF_OK) return bail(st);
@@ -498,16 +551,26 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   if ((st = upload(pl, &pl->tw_x32, tofc(twx))) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->twp32, tofc(twp))) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
-  if ((st = dalloc(pl, &pl->d_special_scratch, pl->special.size() * 3 * (size_t)ny)) != CF_OK) return bail(st);
+  {
+    std::vector<double> den(pl->special.size() * (size_t)ny), cpv(den.size());
+    for (size_t l = 0; l < pl->special.size(); ++l)
+      special_factors(pl, pl->special[l], den.data() + l * ny, cpv.data() + l * ny);
+    if ((st = upload(pl, &pl->d_special_den, den)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_special_cp, cpv)) != CF_OK) return bail(st);
+  }
   const size_t nspec = (size_t)ny * pl->nkx * nz;
   if (opt.precision == CF_FP64) {
-    cx<double>* sp = nullptr;
-    if ((st = dalloc(pl, &sp, nspec)) != CF_OK) return bail(st);
-    pl->spec = sp;
+    cx<double>*a = nullptr, *b = nullptr;
+    if ((st = dalloc(pl, &a, nspec)) != CF_OK) return bail(st);
+    if ((st = dalloc(pl, &b, nspec)) != CF_OK) return bail(st);
+    pl->specA = a;
+    pl->specB = b;
   } else {
-    cx<float>* sp = nullptr;
-    if ((st = dalloc(pl, &sp, nspec)) != CF_OK) return bail(st);
-    pl->spec = sp;
+    cx<float>*a = nullptr, *b = nullptr;
+    if ((st = dalloc(pl, &a, nspec)) != CF_OK) return bail(st);
+    if ((st = dalloc(pl, &b, nspec)) != CF_OK) return bail(st);
+    pl->specA = a;
+    pl->specB = b;
   }
   *out = pl;
   return CF_OK;
@@ -545,13 +608,13 @@ cf_status cf_forward_spectral(cf_plan* pl, const double* f, void* fhat, void* st
   return forward_t<double>(pl, f, static_cast<cx<double>*>(fhat), s);
 }
 
-cf_status cf_inverse_spectral(cf_plan* pl, void* phat, double* p, void* stream) {
+cf_status cf_inverse_spectral(cf_plan* pl, const void* phat, double* p, void* stream) {
   CF_TRY(check_plan(pl));
   CF_TRY(check_ptr(phat, "phat"));
   CF_TRY(check_ptr(p, "p"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (pl->mixed()) return inverse_t<float>(pl, static_cast<cx<float>*>(phat), p, s);
-  return inverse_t<double>(pl, static_cast<cx<double>*>(phat), p, s);
+  if (pl->mixed()) return inverse_t<float>(pl, static_cast<const cx<float>*>(phat), p, s);
+  return inverse_t<double>(pl, static_cast<const cx<double>*>(phat), p, s);
 }
 
 cf_status cf_solve_spectral(cf_plan* pl, const void* fhat, void* phat, void* stream) {

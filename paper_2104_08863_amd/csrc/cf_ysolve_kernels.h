@@ -1,6 +1,7 @@
 // Wall-normal solves of the spectral lines (Section 2.1, Eq. (9) corrected;
-// Section 2.2 PDD).  Spectral layout [ny][nx/2+1][nz]; line l = kx*nz + kz,
-// row stride (nx/2+1)*nz.
+// Section 2.2 PDD).  Spectral layout B = [nx/2+1][ny][nz]: line l = kx*nz + kz
+// starts at kx*ny*nz + kz and has row stride nz, so a block of consecutive
+// lines stays inside one contiguous kx-slab.
 //
 // k_ysolve: a block owns LB consecutive lines (consecutive kz, so every row
 // access of the block is a contiguous run of LB complex values); each line is
@@ -58,7 +59,7 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   T* s_vm = s_v1 + P * LB;
   T* s_w1 = s_vm + P * LB;
   T* s_wm = s_w1 + P * LB;
-  zrow<T>* s_z = reinterpret_cast<zrow<T>*>(s_wm + P * LB);
+  const zrow_soa<T> s_z{s_wm + P * LB, P * LB};
 
   for (int j = threadIdx.x; j < ny; j += blockDim.x) {
     sa[j] = acoef[j];
@@ -71,9 +72,9 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   const int kx = ok ? int(line / ya.nz) : 0;
   const int kz = ok ? int(line % ya.nz) : 1;
   const T k2 = ok ? kx2[kx] + kz2[kz] : T(1);
-  const long rs = (long)ya.nkx * ya.nz;
+  const long rs = ya.nz;
   const int j0 = i * M;
-  const long base = (ok ? line : 0) + (long)j0 * rs;
+  const long base = (long)kx * ny * ya.nz + kz + (long)j0 * rs;
 
   cx<T> d[M];
   T v[M], w[M];
@@ -105,11 +106,13 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
       z = zrow_make(s_vm[me], s_wm[me], s_v1[nx_], s_w1[nx_], s_xm[me], s_x1[nx_]);
     }
     for (int st = 1; st < Q; st *= 2) {
-      if (i < Q) s_z[me] = z;
+      if (i < Q) s_z.put(me, z);
       __syncthreads();
       if (i < Q) {
         const bool hl = i - st >= 0, hh = i + st < Q;
-        z = zrow_reduce(z, &s_z[(hl ? i - st : i) * LB + q], hl, &s_z[(hh ? i + st : i) * LB + q], hh);
+        const zrow<T> lo = s_z.get((hl ? i - st : i) * LB + q);
+        const zrow<T> hi = s_z.get((hh ? i + st : i) * LB + q);
+        z = zrow_reduce(z, &lo, hl, &hi, hh);
       }
       __syncthreads();
     }
@@ -129,75 +132,132 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   }
 }
 
-// FP64 Thomas on whole lines, one thread per line.  lines[]: line indices;
-// scratch: 3 * ny doubles per line (eliminated upper coefficient and the two
-// parts of the eliminated right-hand side, then of the solution).  The k^2 = 0
+// FP64 Thomas on whole lines, one block per line.  The elimination factors
+// of each listed line (den_j = b_j - a_j cp_{j-1}, cp_j = c_j / den_j, with the
+// top row left out for the k^2 = 0 line) come from the plan.  The k^2 = 0
 // line is made compatible (dy-weighted mean of the RHS removed), solved with
-// its top unknown pinned to zero, and shifted to zero dy-weighted mean.  Reads
-// of fin all precede writes of pout, so the two may alias.
+// its top unknown pinned to zero, and shifted to zero dy-weighted mean.  The
+// line is staged in LDS; reads of fin all precede writes of pout, so the two
+// may alias.  The sweeps follow the textbook operation order without
+// contraction, like the reference definition.
 template <typename T>
-__global__ void k_special_lines(const cx<T>* fin, cx<T>* pout,
-                                const double* __restrict__ a, const double* __restrict__ c,
-                                const double* __restrict__ dy, const double* __restrict__ kx2,
-                                const double* __restrict__ kz2, const int* __restrict__ lines,
-                                int n_lines, double* __restrict__ scratch, int ny, int nz, int nkx) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= n_lines) return;
+__global__ void __launch_bounds__(256)
+k_special_lines(const cx<T>* fin, cx<T>* pout, const double* __restrict__ a,
+                const double* __restrict__ den, const double* __restrict__ cpt,
+                const double* __restrict__ dy, const int* __restrict__ lines, int ny, int nz) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) double sm[];
+  double* fr = sm;
+  double* fi = fr + ny;
+  double* sa = fi + ny;
+  double* sd = sa + ny;
+  double* sc = sd + ny;
+  double* red = sc + ny;  // 3 * blockDim doubles
+  const int l = blockIdx.x;
   const long line = lines[l];
   const int kx = int(line / nz), kz = int(line % nz);
-  const double k2 = kx2[kx] + kz2[kz];
-  const long rs = (long)nkx * nz;
-  double* cp = scratch + (long)l * 3 * ny;
-  double* xr = cp + ny;
-  double* xi = xr + ny;
+  const long base = (long)kx * ny * nz + kz;
   const bool mean_line = (kx == 0 && kz == 0);
-  double sw = 0.0;
-  for (int j = 0; j < ny; ++j) sw += dy[j];
-  double mr = 0.0, mi = 0.0;
-  if (mean_line) {
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < ny; ++j) {
-      const cx<T> f = fin[line + j * rs];
-      sr += dy[j] * double(f.re);
-      si += dy[j] * double(f.im);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = tid; j < ny; j += nt) {
+    const cx<T> f = fin[base + (long)j * nz];
+    fr[j] = double(f.re);
+    fi[j] = double(f.im);
+    sa[j] = a[j];
+    sd[j] = den[(long)l * ny + j];
+    sc[j] = cpt[(long)l * ny + j];
+  }
+  __syncthreads();
+  // dy-weighted means (block reduction), used by the k^2 = 0 line only
+  auto wmean = [&](double& mr, double& mi) {
+    double r = 0.0, im = 0.0, w = 0.0;
+    for (int j = tid; j < ny; j += nt) {
+      r += dy[j] * fr[j];
+      im += dy[j] * fi[j];
+      w += dy[j];
     }
-    mr = sr / sw;
-    mi = si / sw;
+    red[tid] = r;
+    red[nt + tid] = im;
+    red[2 * nt + tid] = w;
+    __syncthreads();
+    for (int h = nt / 2; h > 0; h /= 2) {
+      if (tid < h) {
+        red[tid] += red[tid + h];
+        red[nt + tid] += red[nt + tid + h];
+        red[2 * nt + tid] += red[2 * nt + tid + h];
+      }
+      __syncthreads();
+    }
+    mr = red[0] / red[2 * nt];
+    mi = red[nt] / red[2 * nt];
+    __syncthreads();
+  };
+  if (mean_line) {
+    double mr, mi;
+    wmean(mr, mi);
+    for (int j = tid; j < ny; j += nt) {
+      fr[j] = fr[j] - mr;
+      fi[j] = fi[j] - mi;
+    }
+    __syncthreads();
   }
   const int n = mean_line ? ny - 1 : ny;
-  for (int j = 0; j < n; ++j) {
-    const cx<T> f = fin[line + j * rs];
-    const double fr = double(f.re) - mr, fi = double(f.im) - mi;
-    const double b = -(a[j] + c[j]) - k2;
-    const double cj = (j == n - 1) ? 0.0 : c[j];
-    if (j == 0) {
-      cp[j] = cj / b;
-      xr[j] = fr / b;
-      xi[j] = fi / b;
-    } else {
-      const double den = b - a[j] * cp[j - 1];
-      cp[j] = cj / den;
-      xr[j] = (fr - a[j] * xr[j - 1]) / den;
-      xi[j] = (fi - a[j] * xi[j - 1]) / den;
+  if (tid == 0) {
+    // sweeps in chunks of 8 rows whose operands are read before the chain
+    constexpr int C = 8;
+    double xr = fr[0] / sd[0], xi = fi[0] / sd[0];
+    fr[0] = xr;
+    fi[0] = xi;
+    for (int j0 = 1; j0 < n; j0 += C) {
+      double ar[C], br[C], bi[C], dr[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int j = j0 + u < n ? j0 + u : n - 1;
+        ar[u] = sa[j];
+        br[u] = fr[j];
+        bi[u] = fi[j];
+        dr[u] = sd[j];
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        if (j0 + u < n) {
+          const double tr = ar[u] * xr, ti = ar[u] * xi;
+          xr = (br[u] - tr) / dr[u];
+          xi = (bi[u] - ti) / dr[u];
+          fr[j0 + u] = xr;
+          fi[j0 + u] = xi;
+        }
+      }
+    }
+    for (int j0 = n - 2; j0 >= 0; j0 -= C) {
+      double cr[C], br[C], bi[C];
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        const int j = j0 - u >= 0 ? j0 - u : 0;
+        cr[u] = sc[j];
+        br[u] = fr[j];
+        bi[u] = fi[j];
+      }
+#pragma unroll
+      for (int u = 0; u < C; ++u) {
+        if (j0 - u >= 0) {
+          const double tr = cr[u] * xr, ti = cr[u] * xi;
+          xr = br[u] - tr;
+          xi = bi[u] - ti;
+          fr[j0 - u] = xr;
+          fi[j0 - u] = xi;
+        }
+      }
+    }
+    if (mean_line) {
+      fr[ny - 1] = 0.0;
+      fi[ny - 1] = 0.0;
     }
   }
-  for (int j = n - 2; j >= 0; --j) {
-    xr[j] = xr[j] - cp[j] * xr[j + 1];
-    xi[j] = xi[j] - cp[j] * xi[j + 1];
-  }
-  double or_ = 0.0, oi = 0.0;
-  if (mean_line) {
-    xr[ny - 1] = 0.0;
-    xi[ny - 1] = 0.0;
-    double sr = 0.0, si = 0.0;
-    for (int j = 0; j < ny; ++j) {
-      sr += dy[j] * xr[j];
-      si += dy[j] * xi[j];
-    }
-    or_ = sr / sw;
-    oi = si / sw;
-  }
-  for (int j = 0; j < ny; ++j) pout[line + j * rs] = mk(T(xr[j] - or_), T(xi[j] - oi));
+  __syncthreads();
+  double orr = 0.0, oi = 0.0;
+  if (mean_line) wmean(orr, oi);
+  for (int j = tid; j < ny; j += nt) pout[base + (long)j * nz] = mk(T(fr[j] - orr), T(fi[j] - oi));
 }
 
 }  // namespace cf

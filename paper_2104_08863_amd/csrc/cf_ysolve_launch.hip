@@ -62,15 +62,14 @@ size_t ysolve_lds_needed(int ny, int P, bool fp64) {
 }
 
 template <typename T>
-hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* c,
-                                const double* dy, const double* kx2, const double* kz2,
-                                const int* lines, int n_lines, double* scratch, int ny, int nz,
-                                int nkx, hipStream_t s) {
+hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* den,
+                                const double* cp, const double* dy, const int* lines, int n_lines,
+                                int ny, int nz, hipStream_t s) {
   if (n_lines <= 0) return hipSuccess;
-  const int th = 64;
-  const int blocks = (n_lines + th - 1) / th;
-  hipLaunchKernelGGL((k_special_lines<T>), dim3(blocks), dim3(th), 0, s, fin, pout, a, c, dy, kx2, kz2,
-                     lines, n_lines, scratch, ny, nz, nkx);
+  const int th = 256;
+  const size_t lds = sizeof(double) * (5 * (size_t)ny + 3 * th);
+  hipLaunchKernelGGL((k_special_lines<T>), dim3(n_lines), dim3(th), lds, s, fin, pout, a, den, cp, dy, lines,
+                     ny, nz);
   return hipGetLastError();
 }
 
@@ -78,8 +77,8 @@ hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, 
   template hipError_t launch_ysolve<T>(const YLaunch&, const cx<T>*, cx<T>*, const T*, const T*,   \
                                        const T*, const T*, T, hipStream_t);                        \
   template hipError_t launch_special_lines<T>(const cx<T>*, cx<T>*, const double*, const double*, \
-                                              const double*, const double*, const double*,        \
-                                              const int*, int, double*, int, int, int, hipStream_t);
+                                              const double*, const double*, const int*, int, int, int, \
+                                              hipStream_t);
 CF_INST(double)
 CF_INST(float)
 #undef CF_INST

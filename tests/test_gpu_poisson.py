@@ -44,10 +44,11 @@ def test_forward_and_inverse_transforms(nx, ny, nz, gamma, parts):
     f = synth.uniform_rhs(nx, ny, nz, seed=1)
     fg = torch.tensor(f, device=dev())
     fh = pl.forward_spectral(fg)
-    ref = O.forward_transform(torch.tensor(f)).permute(0, 2, 1).numpy()   # (ny, nkx, nz)
+    ref = O.forward_transform(torch.tensor(f)).permute(2, 0, 1).numpy()   # (nkx, ny, nz)
     got = fh.cpu().numpy()
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
     back = pl.inverse_spectral(fh).cpu().numpy()
+    assert torch.equal(fh.cpu(), torch.tensor(got))   # input spectrum left intact
     assert np.abs(back - f).max() <= 1e-14 * max(1.0, np.log2(nx * nz))
 
 
@@ -55,12 +56,12 @@ def test_forward_and_inverse_transforms(nx, ny, nz, gamma, parts):
 def test_solve_spectral_per_mode(nx, ny, nz, gamma, parts):
     pl, box = plan_for(nx, ny, nz, gamma, parts)
     rng = np.random.default_rng(2)
-    fh = rng.standard_normal((ny, nx // 2 + 1, nz)) + 1j * rng.standard_normal((ny, nx // 2 + 1, nz))
-    fh[:, 0, 0].imag = 0.0
+    fh = rng.standard_normal((nx // 2 + 1, ny, nz)) + 1j * rng.standard_normal((nx // 2 + 1, ny, nz))
+    fh[0, :, 0].imag = 0.0
     fg = torch.tensor(fh, device=dev())
     ph = pl.solve_spectral(fg).cpu().numpy()
-    ref = O.solve_spectral(torch.tensor(fh).permute(0, 2, 1), box).permute(0, 2, 1).numpy()
-    err = np.abs(ph - ref).max(axis=0) / np.abs(ref).max(axis=0)      # per (kx, kz) line
+    ref = O.solve_spectral(torch.tensor(fh).permute(1, 2, 0), box).permute(2, 0, 1).numpy()
+    err = np.abs(ph - ref).max(axis=1) / np.abs(ref).max(axis=1)      # per (kx, kz) line
     assert err.max() <= 1e-11, f"worst line {np.unravel_index(err.argmax(), err.shape)}: {err.max():.3e}"
     # in place
     ph2 = pl.solve_spectral(fg, out=fg).cpu().numpy()
@@ -78,13 +79,14 @@ def test_drop_path_matches_oracle_pdd():
     info = pl.info()
     assert 0 < info["n_drop_lines"] < info["n_lines"]
     rng = np.random.default_rng(4)
-    fh = rng.standard_normal((ny, nx // 2 + 1, nz)) + 1j * rng.standard_normal((ny, nx // 2 + 1, nz))
-    ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy()
+    fh = rng.standard_normal((nx // 2 + 1, ny, nz)) + 1j * rng.standard_normal((nx // 2 + 1, ny, nz))
+    ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy().transpose(1, 0, 2)  # (ny, nkx, nz)
+    fh = fh.transpose(1, 0, 2)
     a, c, k2 = O.line_coefficients(box)
     k2 = k2.numpy().T                                                    # (nkx, nz)
     sel = np.argwhere(k2 >= info["k2_threshold"])
     b = -(a + c)[:, None] - torch.tensor(k2[sel[:, 0], sel[:, 1]])[None, :]
-    d = torch.tensor(fh[:, sel[:, 0], sel[:, 1]])
+    d = torch.tensor(np.ascontiguousarray(fh[:, sel[:, 0], sel[:, 1]]))
     ref_drop = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
     ref_exact = O.thomas(a[:, None], b, c[:, None], d).numpy()
     got = ph[:, sel[:, 0], sel[:, 1]]
