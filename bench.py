@@ -26,50 +26,63 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
-def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_phys: int = 8) -> float:
-    """Algorithmic bytes of one launch of a kernel class (arrays touched once)."""
+def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_phys: int = 8,
+                 fused_div: bool = False) -> float:
+    """Algorithmic bytes of one launch of a kernel class: every array the
+    kernel must read or write, once (no halo re-reads counted)."""
     nkx = nx // 2 + 1
     phys = nx * ny * nz * esize_phys
     spec = ny * nkx * nz * 2 * esize_spec
     return {
-        "r2c_x": phys + spec,
+        "r2c_x": (3 * phys if fused_div else phys) + spec,
         "fft_z_fwd": 2 * spec,
         "ysolve": 2 * spec,
         "fft_z_inv": 2 * spec,
-        "c2r_x": spec + phys,
+        "c2r_x": spec + nx * ny * nz * 8,
         "divergence": 4 * phys,
         "special_lines": 0.0,
+        "rk_stage1": 6 * phys,
+        "rk_stage2": 9 * phys,
+        "correct": 6 * phys + nx * ny * nz * 8,
     }[name]
 
 
-def cpu_baseline(wl, seconds_target: float = 20.0):
-    """The oracle's Poisson solve on a bounded sample of the workload: the same
-    nx x nz planes and y-grid shape with ny reduced so one solve takes well
-    under the target; Mpts/s = sample points / wall time."""
+def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
+    """The oracle (plain torch CPU, FP64) on a bounded sample of the workload:
+    the same nx x nz planes and y-grid shape with ny reduced so a few calls fit
+    in the time target; Mpts/s = sample points / wall time per call."""
     import torch
 
     import oracle as O
     from paper_2104_08863_amd import synth
     threads = torch.get_num_threads()
+    budget = 7.0e7 if poisson_only else 8.5e6
     ny_s = wl.ny
-    # budget: ~7e7 points per solve keeps one oracle call in the seconds range
-    while ny_s > 8 and wl.nx * wl.nz * ny_s > 7.0e7:
+    while ny_s > 8 and wl.nx * wl.nz * ny_s > budget:
         ny_s //= 2
-    box = O.Box(wl.nx, ny_s, wl.nz, wl.lx, wl.lz, synth.tanh_faces(ny_s, wl.gamma))
-    f = torch.tensor(synth.uniform_rhs(wl.nx, ny_s, wl.nz, seed=0))
-    O.poisson(f, box)  # warm-up
+    yf = synth.tanh_faces(ny_s, wl.gamma)
+    box = O.Box(wl.nx, ny_s, wl.nz, wl.lx, wl.lz, yf)
+    if poisson_only:
+        f = torch.tensor(synth.uniform_rhs(wl.nx, ny_s, wl.nz, seed=0))
+        call = lambda: O.poisson(f, box)  # noqa: E731
+        what = "Poisson solve (torch CPU FFT + Thomas)"
+    else:
+        u, v, w = (torch.tensor(q) for q in synth.perturbed_poiseuille(wl.nx, ny_s, wl.nz, yf, seed=0))
+        call = lambda: O.projection_step(u, v, w, box, wl.dt, wl.nu, wl.fx)  # noqa: E731
+        what = "projection step (RK2 + torch CPU FFT/Thomas Poisson + correction)"
+    call()  # warm-up
     t0 = time.perf_counter()
     n = 0
     while True:
-        O.poisson(f, box)
+        call()
         n += 1
         if time.perf_counter() - t0 > seconds_target / 4 or n >= 3:
             break
     dt = (time.perf_counter() - t0) / n
     npts = wl.nx * ny_s * wl.nz
-    return {"value": npts / dt / 1e6, "unit": "Mpts/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle Poisson solve (torch CPU FFT + Thomas) on {wl.nx}x{ny_s}x{wl.nz} "
-                      f"(the workload's x-z planes, ny reduced from {wl.ny}), mean of {n} solves"}
+    return {"value": round(npts / dt / 1e6, 2), "unit": "Mpts/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle {what} on {wl.nx}x{ny_s}x{wl.nz} (the workload's x-z planes, "
+                      f"ny reduced from {wl.ny}), mean of {n} calls"}
 
 
 def main():
@@ -79,6 +92,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="step550")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="time the Poisson solve alone instead of the projection step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -94,13 +109,22 @@ def main():
     torch.cuda.set_device(dev)
     wl = synth.WORKLOADS[args.workload]
     yf = wl.y_faces()
-    plan = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64")
+    plan = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64", step=not args.poisson_only)
     info = plan.info()
-    f = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0), device=dev)
-    p = torch.empty_like(f)
+    if args.poisson_only:
+        f = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0), device=dev)
+        p = torch.empty_like(f)
 
-    def step():
-        plan.poisson_solve(f, out=p)
+        def step():
+            plan.poisson_solve(f, out=p)
+    else:
+        u, v, w = (torch.tensor(q, device=dev) for q in
+                   synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0))
+        outs = tuple(torch.empty_like(u) for _ in range(3))
+        p = torch.empty_like(u)
+
+        def step():
+            plan.projection_step(u, v, w, wl.dt, wl.nu, wl.fx, out=outs, p=p)
 
     for _ in range(args.warmup):
         step()
@@ -119,17 +143,21 @@ def main():
     npts = wl.nx * wl.ny * wl.nz
     value = npts / (ms * 1e-3) / 1e6
 
+    fused = not args.poisson_only
+    kb = lambda k: kernel_bytes(k, wl.nx, wl.ny, wl.nz, 8, fused_div=fused)  # noqa: E731
     kern = {k: v for k, v in tim.items() if v[1] > 0}
     dom = max(kern, key=lambda k: kern[k][0])
     avg_ms = kern[dom][0] / kern[dom][1]
-    nbytes = kernel_bytes(dom, wl.nx, wl.ny, wl.nz, 8)
+    nbytes = kb(dom)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     per_kernel = {k: {"avg_us": round(v[0] / v[1] * 1e3, 2), "launches": v[1],
-                      "GBps": round(kernel_bytes(k, wl.nx, wl.ny, wl.nz, 8) / (v[0] / v[1] * 1e-3) / 1e9, 1)}
+                      "GBps": round(kb(k) / (v[0] / v[1] * 1e-3) / 1e9, 1)}
                   for k, v in kern.items()}
-    model_bytes = sum(kernel_bytes(k, wl.nx, wl.ny, wl.nz, 8) * v[1] for k, v in kern.items()) / args.steps
+    model_bytes = sum(kb(k) * v[1] for k, v in kern.items()) / args.steps
+    what = "FP64 pressure-Poisson solve" if args.poisson_only else "FP64 projection step (RK2 + Poisson + correction)"
     out = {
-        "metric": "Mpts/s per FP64 Poisson solve (FFT x,z + PDD y), % HBM",
+        "metric": ("Mpts/s per FP64 Poisson solve (FFT x,z + PDD y), % HBM" if args.poisson_only
+                   else "Mpts/s per FP64 projection step (RK2 + FFT/PDD Poisson + correction), % HBM"),
         "value": round(value, 1),
         "unit": "Mpts/s",
         "n_gpus": 1,
@@ -141,8 +169,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: FP64 pressure-Poisson solve {wl.nx}x{wl.ny}x{wl.nz}, "
-                               f"tanh y-grid factor {wl.gamma}, box {wl.lx:.4f}x{wl.lz:.4f}",
+        "config": {"workload": f"{wl.name}: {what} {wl.nx}x{wl.ny}x{wl.nz}, "
+                               f"tanh y-grid factor {wl.gamma}, box {wl.lx:.4f}x{wl.lz:.4f}, "
+                               f"dt {wl.dt}, nu {wl.nu:.6g}",
                    "nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "precision": "fp64",
                    "pdd_parts": info["n_parts"], "drop_lines": info["n_drop_lines"],
                    "lines": info["n_lines"]},
@@ -153,7 +182,7 @@ def main():
         "kernels": per_kernel,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, args.poisson_only)
     print(json.dumps(out), flush=True)
 
 

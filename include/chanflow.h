@@ -65,7 +65,10 @@ typedef struct {
   int fp64_kx;        /* CF_MIXED: lines with kx < fp64_kx and min(kz, nz-kz) < fp64_kz */
   int fp64_kz;        /*   are solved in FP64 (default 4, 4) */
   int refine_passes;  /* CF_MIXED: FP64 residual + correction solves (default 1) */
+  int flags;          /* CF_PLAN_STEP: also allocate the projection-step workspace */
 } cf_options;
+
+enum { CF_PLAN_STEP = 1 };
 
 typedef struct {
   int nx, ny, nz, precision;
@@ -117,6 +120,22 @@ cf_status cf_poisson_solve(cf_plan* plan, const double* f, double* p, void* stre
 cf_status cf_divergence(cf_plan* plan, const double* u, const double* v, const double* w,
                         double* f, double scale, void* stream);
 
+/*
+ * One projection step (Section 2, Eq. (3)-(7)): explicit RK2 (Heun, Eq. (5)-(6)) of
+ *   du/dt = R(u) = -N(u) + nu lap(u) + fx e_x
+ * giving u*, then the pressure solve L_h p = D u* / dt and u1 = u* - dt G p (Eq. (4)),
+ * so that D u1 = 0 to round-off.  N(u) = div(u u) in flux form (linear interpolation,
+ * the y-interpolation to a face weighted by the two cell heights); lap uses the no-slip
+ * ghost mirrored about the wall; v = 0 on both walls.
+ * u, v, w: device inputs (ny, nz, nx); u1, v1, w1: outputs (may alias the inputs);
+ * p: device double output (ny, nz, nx) or NULL (pressure kept in the plan workspace).
+ * Velocity arrays are double for CF_FP64 plans and float for CF_MIXED plans.
+ * The plan must have been created with CF_PLAN_STEP in opt->flags.
+ */
+cf_status cf_projection_step(cf_plan* plan, const void* u, const void* v, const void* w, void* u1,
+                             void* v1, void* w1, double* p, double dt, double nu, double fx,
+                             void* stream);
+
 /* Test hook, steps (2)-(4): forward real transform in x then complex transform in z of f
  * (device double (ny, nz, nx)) into fhat (device complex, plan precision: double pairs
  * for CF_FP64, float pairs for CF_MIXED; shape (nx/2+1, ny, nz)). */
@@ -145,7 +164,10 @@ enum {
   CF_K_FFT_Z_INV = 4, /* inverse complex transform along z */
   CF_K_C2R_X = 5,     /* inverse real transform along x (+ fused consumers) */
   CF_K_DIVERGENCE = 6,
-  CF_K_COUNT = 7
+  CF_K_RK1 = 7,       /* RK2 stage 1 (momentum RHS) */
+  CF_K_RK2 = 8,       /* RK2 stage 2 (momentum RHS) */
+  CF_K_CORRECT = 9,   /* pressure-gradient correction u1 = u* - dt G p */
+  CF_K_COUNT = 10
 };
 cf_status cf_plan_set_timing(cf_plan* plan, int enable);
 cf_status cf_plan_reset_timing(cf_plan* plan);

@@ -15,12 +15,15 @@ HOSTLIB_PATH = os.path.join(PKG, "libchanflow_host.so")
 
 CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMERIC = range(6)
 CF_FP64, CF_MIXED = 0, 1
-KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence"]
+KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
+           "rk_stage1", "rk_stage2", "correct"]
+CF_PLAN_STEP = 1
 
 
 class cf_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_parts", C.c_int), ("drop_tol", C.c_double),
-                ("fp64_kx", C.c_int), ("fp64_kz", C.c_int), ("refine_passes", C.c_int)]
+                ("fp64_kx", C.c_int), ("fp64_kz", C.c_int), ("refine_passes", C.c_int),
+                ("flags", C.c_int)]
 
 
 class cf_plan_info(C.Structure):
@@ -42,6 +45,7 @@ SIGNATURES = {
     "cf_plan_query": (_I, [_P, C.POINTER(cf_plan_info)]),
     "cf_poisson_solve": (_I, [_P, _P, _P, _P]),
     "cf_divergence": (_I, [_P, _P, _P, _P, _P, _D, _P]),
+    "cf_projection_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
     "cf_forward_spectral": (_I, [_P, _P, _P, _P]),
     "cf_inverse_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral": (_I, [_P, _P, _P, _P]),

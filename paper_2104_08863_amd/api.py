@@ -25,7 +25,7 @@ class Plan:
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
                  precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
                  fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
-                 device=None):
+                 step: bool = False, device=None):
         lib = L.lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nkx = self.nx // 2 + 1
@@ -45,6 +45,7 @@ class Plan:
         opt.fp64_kx = int(fp64_kx)
         opt.fp64_kz = int(fp64_kz)
         opt.refine_passes = int(refine_passes)
+        opt.flags = L.CF_PLAN_STEP if step else 0
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -52,6 +53,7 @@ class Plan:
                                     yf.ctypes.data_as(C.POINTER(C.c_double)), C.byref(opt))
         L.check(st, "cf_plan_create")
         self.spec_dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.state_dtype = torch.float64 if precision == "fp64" else torch.float32
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -133,6 +135,23 @@ class Plan:
         out = self._new() if out is None else self._field(out, "out")
         L.check(L.lib().cf_divergence(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out), float(scale),
                                       _stream()), "cf_divergence")
+        return out
+
+    def projection_step(self, u, v, w, dt: float, nu: float, fx: float, out=None, p=None):
+        """One RK2 + pressure-projection step; returns (u1, v1, w1).  out: optional
+        (u1, v1, w1) tensors (may be u, v, w themselves); p: optional float64
+        tensor receiving the pressure."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w")):
+            self._field(t, n, sd)
+        if out is None:
+            out = (self._new(sd), self._new(sd), self._new(sd))
+        for t, n in zip(out, ("u1", "v1", "w1")):
+            self._field(t, n, sd)
+        pp = None if p is None else _ptr(self._field(p, "p"))
+        L.check(L.lib().cf_projection_step(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out[0]), _ptr(out[1]),
+                                           _ptr(out[2]), pp, float(dt), float(nu), float(fx), _stream()),
+                "cf_projection_step")
         return out
 
     def forward_spectral(self, f: torch.Tensor, out=None) -> torch.Tensor:

@@ -136,6 +136,48 @@ struct SrcPlain {
   }
 };
 
+// Divergence of a staggered velocity field times `scale` (Eq. (7) right-hand
+// side), produced on the fly: f_i = [(u_i - u_{i-1})/dx + (v_j - v_{j-1})/dy_j
+// + (w_k - w_{k-1})/dz] * scale with v = 0 on both walls.
+template <typename T, typename Ts>
+struct SrcDiv {
+  const Ts* __restrict__ u;
+  const Ts* __restrict__ v;
+  const Ts* __restrict__ w;
+  const double* __restrict__ rdy;
+  double rdx, rdz, scale;
+  int nx, ny, nz;
+  __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
+    const long row = ((long)j * nz + k) * nx;
+    const long plane = (long)nz * nx;
+    const int km = (k == 0) ? nz - 1 : k - 1;
+    const long rowm = ((long)j * nz + km) * nx;
+    const int i0 = 2 * m, i1 = 2 * m + 1, im = (m == 0) ? nx - 1 : 2 * m - 1;
+    const cx<Ts> up = reinterpret_cast<const cx<Ts>*>(u + row)[m];
+    const double uim = double(u[row + im]);
+    const cx<Ts> wp = reinterpret_cast<const cx<Ts>*>(w + row)[m];
+    const cx<Ts> wmp = reinterpret_cast<const cx<Ts>*>(w + rowm)[m];
+    double v0 = 0.0, v1 = 0.0, vm0 = 0.0, vm1 = 0.0;
+    if (j < ny - 1) {
+      const cx<Ts> vp = reinterpret_cast<const cx<Ts>*>(v + row)[m];
+      v0 = double(vp.re);
+      v1 = double(vp.im);
+    }
+    if (j > 0) {
+      const cx<Ts> vmp = reinterpret_cast<const cx<Ts>*>(v + row - plane)[m];
+      vm0 = double(vmp.re);
+      vm1 = double(vmp.im);
+    }
+    const double r = rdy[j];
+    const double f0 = ((double(up.re) - uim) * rdx + (v0 - vm0) * r + (double(wp.re) - double(wmp.re)) * rdz) * scale;
+    const double f1 = ((double(up.im) - double(up.re)) * rdx + (v1 - vm1) * r +
+                       (double(wp.im) - double(wmp.im)) * rdz) * scale;
+    (void)i0;
+    (void)i1;
+    return mk(T(f0), T(f1));
+  }
+};
+
 template <typename T, int NH, typename Src>
 __global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
 k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ twp,

@@ -72,6 +72,22 @@ hipError_t launch_r2c_plain(int nh, const double* f, cx<T>* spec, const cx<T>* t
   }
 }
 
+template <typename T>
+hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double* w, const double* rdy,
+                          double rdx, double rdz, double scale, cx<T>* spec, const cx<T>* tw,
+                          const cx<T>* twp, int ny, int nz, hipStream_t s) {
+  SrcDiv<T, double> src{u, v, w, rdy, rdx, rdz, scale, 2 * nh, ny, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return r2c_n<T, N>(src, spec, tw, twp, ny, nz, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int NH, typename Dst>
 static hipError_t c2r_n(const cx<T>* spec, Dst dst, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
                         T scale, hipStream_t s) {
@@ -103,7 +119,10 @@ hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* t
   template hipError_t launch_r2c_plain<T>(int, const double*, cx<T>*, const cx<T>*, const cx<T>*, int, \
                                           int, hipStream_t);                                         \
   template hipError_t launch_c2r_plain<T>(int, const cx<T>*, double*, const cx<T>*, const cx<T>*, int, \
-                                          int, T, hipStream_t);
+                                          int, T, hipStream_t);                                      \
+  template hipError_t launch_r2c_div<T>(int, const double*, const double*, const double*, const double*, \
+                                        double, double, double, cx<T>*, const cx<T>*, const cx<T>*,  \
+                                        int, int, hipStream_t);
 CF_INST(double)
 CF_INST(float)
 #undef CF_INST

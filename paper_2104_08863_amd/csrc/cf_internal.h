@@ -51,6 +51,20 @@ hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, 
 
 bool ysolve_m_compiled(int m);
 
+template <typename T>
+struct Geo;
+
+// RK2 stages of the momentum equation: stage 1 out = f + dt R(f); stage 2
+// out = (f0 + f)/2 + dt/2 R(f).
+template <typename T>
+hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const T* u0, const T* v0,
+                           const T* w0, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu, T fx,
+                           hipStream_t s);
+
+// u1 = us - dt G p in place.
+template <typename T>
+hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s);
+
 // Plain divergence (test hook): f = scale * D(u, v, w).
 hipError_t launch_divergence(const double* u, const double* v, const double* w, double* f,
                              const double* rdy, double rdx, double rdz, double scale, int nx,

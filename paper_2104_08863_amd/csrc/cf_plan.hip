@@ -19,6 +19,7 @@
 #include "cf_fft.h"
 #include "cf_internal.h"
 #include "cf_pdd.h"
+#include "cf_step_kernels.h"
 
 namespace cf {
 size_t ysolve_lds_needed(int ny, int P, bool fp64);
@@ -69,7 +70,8 @@ struct cf_plan {
   size_t bytes = 0;
   // device tables (FP64 and FP32 copies)
   double *d_a = nullptr, *d_c = nullptr, *d_dy = nullptr, *d_rdy = nullptr, *d_kx2 = nullptr,
-         *d_kz2 = nullptr;
+         *d_kz2 = nullptr, *d_rdyc = nullptr, *d_wl = nullptr, *d_wu = nullptr;
+  float *s_rdy = nullptr, *s_rdyc = nullptr, *s_wl = nullptr, *s_wu = nullptr;
   float *s_a = nullptr, *s_c = nullptr, *s_kx2 = nullptr, *s_kz2 = nullptr;
   cx<double>*tw_z64 = nullptr, *tw_x64 = nullptr, *twp64 = nullptr;
   cx<float>*tw_z32 = nullptr, *tw_x32 = nullptr, *twp32 = nullptr;
@@ -80,6 +82,12 @@ struct cf_plan {
   // x side, layout B (nkx, ny, nz) on the wall-normal side
   void* specA = nullptr;
   void* specB = nullptr;
+  // projection-step workspace: RK stage-1 fields (state precision) and pressure
+  void *ub = nullptr, *vb = nullptr, *wb = nullptr;
+  double* pws = nullptr;
+  cf::Geo<double> g64{};
+  cf::Geo<float> g32{};
+
   bool mixed() const { return opt.precision == CF_MIXED; }
   // side stream for the whole-line solves, which overlap the PDD kernel
   hipStream_t aux = nullptr;
@@ -282,6 +290,22 @@ cf_status forward_t(cf_plan* pl, const double* f, cx<T>* outB, hipStream_t s) {
   return CF_OK;
 }
 
+// scale * D(u, v, w) -> spectrum in layout B (divergence fused into the x transform)
+template <typename T>
+cf_status forward_div_t(cf_plan* pl, const double* u, const double* v, const double* w, double scale,
+                        cx<T>* outB, hipStream_t s) {
+  using TB = Tabs<T>;
+  cx<T>* A = static_cast<cx<T>*>(pl->specA);
+  CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+div launch", [&] {
+    return cf::launch_r2c_div<T>(pl->nh, u, v, w, pl->d_rdy, 1.0 / pl->dx, 1.0 / pl->dz, scale, A,
+                                 TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+  }));
+  CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+    return cf::launch_fft_z<T>(pl->nz, false, A, outB, TB::twz(pl), pl->ny, pl->nkx, s);
+  }));
+  return CF_OK;
+}
+
 // spectrum in layout B -> p (physical), scaled by 1/(nx nz); inB is not modified
 template <typename T>
 cf_status inverse_t(cf_plan* pl, const cx<T>* inB, double* p, hipStream_t s) {
@@ -337,6 +361,29 @@ cf_status poisson_t(cf_plan* pl, const double* f, double* p, hipStream_t s) {
   return CF_OK;
 }
 
+// One FP64 projection step.
+cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w, double* u1, double* v1,
+                 double* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
+  double* ub = static_cast<double*>(pl->ub);
+  double* vb = static_cast<double*>(pl->vb);
+  double* wb = static_cast<double*>(pl->wb);
+  double* pp = p ? p : pl->pws;
+  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
+    return cf::launch_rk_stage<double>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g64, dt, nu, fx, s);
+  }));
+  CF_TRY(timed(pl, CF_K_RK2, s, "rk stage 2", [&] {
+    return cf::launch_rk_stage<double>(2, ub, vb, wb, u, v, w, u1, v1, w1, pl->g64, dt, nu, fx, s);
+  }));
+  cx<double>* B = static_cast<cx<double>*>(pl->specB);
+  CF_TRY(forward_div_t<double>(pl, u1, v1, w1, 1.0 / dt, B, s));
+  CF_TRY(solve_t<double>(pl, B, B, s));
+  CF_TRY(inverse_t<double>(pl, B, pp, s));
+  CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
+    return cf::launch_correct<double>(u1, v1, w1, pp, pl->g64, dt, s);
+  }));
+  return CF_OK;
+}
+
 // Elimination factors of one whole-line solve, in the operation order of the
 // textbook Thomas algorithm (no contraction).
 void special_factors(const cf_plan* pl, int line, double* den, double* cp) {
@@ -376,6 +423,7 @@ void cf_options_default(cf_options* opt) {
   opt->fp64_kx = 4;
   opt->fp64_kz = 4;
   opt->refine_passes = 1;
+  opt->flags = 0;
 }
 
 const char* cf_status_string(cf_status s) {
@@ -550,6 +598,46 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   if ((st = upload(pl, &pl->tw_z32, tofc(twz))) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->tw_x32, tofc(twx))) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->twp32, tofc(twp))) != CF_OK) return bail(st);
+  {
+    std::vector<double> rdyc(std::max(ny - 1, 1)), wl(std::max(ny - 1, 1)), wu(std::max(ny - 1, 1));
+    for (int j = 0; j + 1 < ny; ++j) {
+      rdyc[j] = 1.0 / pl->dyc[j];
+      wl[j] = pl->dy[j + 1] / (pl->dy[j] + pl->dy[j + 1]);
+      wu[j] = pl->dy[j] / (pl->dy[j] + pl->dy[j + 1]);
+    }
+    if ((st = upload(pl, &pl->d_rdyc, rdyc)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_wl, wl)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_wu, wu)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_rdy, tof(rdy))) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_rdyc, tof(rdyc))) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_wl, tof(wl))) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_wu, tof(wu))) != CF_OK) return bail(st);
+    const double rdx = 1.0 / pl->dx, rdz = 1.0 / pl->dz;
+    pl->g64 = cf::Geo<double>{pl->d_rdy, pl->d_rdyc, pl->d_wl, pl->d_wu, rdx, rdz, rdx * rdx, rdz * rdz, nx, ny, nz};
+    pl->g32 = cf::Geo<float>{pl->s_rdy, pl->s_rdyc, pl->s_wl, pl->s_wu, (float)rdx, (float)rdz,
+                             (float)(rdx * rdx), (float)(rdz * rdz), nx, ny, nz};
+  }
+  if (opt.flags & CF_PLAN_STEP) {
+    const size_t npts = (size_t)nx * ny * nz;
+    if (opt.precision == CF_FP64) {
+      double *a = nullptr, *b = nullptr, *c = nullptr;
+      if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
+      if ((st = dalloc(pl, &b, npts)) != CF_OK) return bail(st);
+      if ((st = dalloc(pl, &c, npts)) != CF_OK) return bail(st);
+      pl->ub = a;
+      pl->vb = b;
+      pl->wb = c;
+    } else {
+      float *a = nullptr, *b = nullptr, *c = nullptr;
+      if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
+      if ((st = dalloc(pl, &b, npts)) != CF_OK) return bail(st);
+      if ((st = dalloc(pl, &c, npts)) != CF_OK) return bail(st);
+      pl->ub = a;
+      pl->vb = b;
+      pl->wb = c;
+    }
+    if ((st = dalloc(pl, &pl->pws, npts)) != CF_OK) return bail(st);
+  }
   if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
   {
     std::vector<double> den(pl->special.size() * (size_t)ny), cpv(den.size());
@@ -651,6 +739,25 @@ cf_status cf_divergence(cf_plan* pl, const double* u, const double* v, const dou
   });
 }
 
+cf_status cf_projection_step(cf_plan* pl, const void* u, const void* v, const void* w, void* u1, void* v1,
+                             void* w1, double* p, double dt, double nu, double fx, void* stream) {
+  CF_TRY(check_plan(pl));
+  if (!(pl->opt.flags & CF_PLAN_STEP)) return fail(CF_ERR_ARG, "plan was created without CF_PLAN_STEP");
+  CF_TRY(check_ptr(u, "u"));
+  CF_TRY(check_ptr(v, "v"));
+  CF_TRY(check_ptr(w, "w"));
+  CF_TRY(check_ptr(u1, "u1"));
+  CF_TRY(check_ptr(v1, "v1"));
+  CF_TRY(check_ptr(w1, "w1"));
+  if (p) CF_TRY(check_ptr(p, "p"));
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
+  if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed()) return fail(CF_ERR_UNSUPPORTED, "mixed-precision projection step is not built yet");
+  return step64(pl, static_cast<const double*>(u), static_cast<const double*>(v), static_cast<const double*>(w),
+                static_cast<double*>(u1), static_cast<double*>(v1), static_cast<double*>(w1), p, dt, nu, fx, s);
+}
+
 cf_status cf_plan_set_timing(cf_plan* pl, int enable) {
   CF_TRY(check_plan(pl));
   if (!enable) CF_TRY(harvest(pl));
@@ -679,8 +786,8 @@ cf_status cf_plan_get_timing(cf_plan* pl, int kernel, double* total_ms, long lon
 }
 
 const char* cf_kernel_name(int k) {
-  static const char* names[CF_K_COUNT] = {"r2c_x", "fft_z_fwd", "ysolve", "special_lines",
-                                          "fft_z_inv", "c2r_x", "divergence"};
+  static const char* names[CF_K_COUNT] = {"r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv",
+                                          "c2r_x", "divergence", "rk_stage1", "rk_stage2", "correct"};
   return (k >= 0 && k < CF_K_COUNT) ? names[k] : "unknown";
 }
 

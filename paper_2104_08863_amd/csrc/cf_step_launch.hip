@@ -1,0 +1,40 @@
+// Launch of the RK2 momentum stages and the pressure-gradient correction.
+#include "cf_internal.h"
+#include "cf_step_kernels.h"
+
+namespace cf {
+
+template <typename T>
+hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const T* u0, const T* v0,
+                           const T* w0, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu, T fx,
+                           hipStream_t s) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const int th = 256;
+  const long blocks = (n + th - 1) / th;
+  if (stage == 1)
+    hipLaunchKernelGGL((k_rk_stage<T, 1>), dim3(blocks), dim3(th), 0, s, u, v, w, u0, v0, w0, uo, vo, wo, g,
+                       dt, nu, fx);
+  else
+    hipLaunchKernelGGL((k_rk_stage<T, 2>), dim3(blocks), dim3(th), 0, s, u, v, w, u0, v0, w0, uo, vo, wo, g,
+                       dt, nu, fx);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s) {
+  const long n = (long)g.nx * g.ny * g.nz;
+  const int th = 256;
+  const long blocks = (n + th - 1) / th;
+  hipLaunchKernelGGL((k_correct<T>), dim3(blocks), dim3(th), 0, s, u, v, w, p, g, dt);
+  return hipGetLastError();
+}
+
+#define CF_INST(T)                                                                                     \
+  template hipError_t launch_rk_stage<T>(int, const T*, const T*, const T*, const T*, const T*,        \
+                                         const T*, T*, T*, T*, const Geo<T>&, T, T, T, hipStream_t); \
+  template hipError_t launch_correct<T>(T*, T*, T*, const double*, const Geo<T>&, T, hipStream_t);
+CF_INST(double)
+CF_INST(float)
+#undef CF_INST
+
+}  // namespace cf

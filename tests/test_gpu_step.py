@@ -1,0 +1,93 @@
+"""GPU parity of the FP64 projection step (RK2 momentum stages, fused
+divergence + Poisson solve, pressure-gradient correction) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # nx, ny, nz, gamma, dt, nu
+    (32, 16, 24, 2.0, 1e-3, 1 / 550),
+    (48, 24, 12, 2.5, 4e-4, 1 / 100),
+    (64, 64, 64, 2.0, 1e-3, 1 / 550),
+    (16, 8, 6, 1.0, 1e-2, 1 / 50),
+    (128, 32, 96, 2.5, 2e-4, 1 / 550),
+]
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def setup(nx, ny, nz, gamma, lx=2 * np.pi, lz=np.pi):
+    from paper_2104_08863_amd.api import Plan
+    yf = synth.tanh_faces(ny, gamma)
+    return Plan(nx, ny, nz, lx, lz, yf, step=True), O.Box(nx, ny, nz, lx, lz, yf)
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,dt,nu", CASES)
+def test_projection_step_matches_oracle(nx, ny, nz, gamma, dt, nu):
+    pl, box = setup(nx, ny, nz, gamma)
+    fx = 3 * nu
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=0)
+    ug, vg, wg = (torch.tensor(q, device=dev()) for q in (u, v, w))
+    p = torch.empty_like(ug)
+    u1, v1, w1 = pl.projection_step(ug, vg, wg, dt, nu, fx, p=p)
+    ref = O.projection_step(*(torch.tensor(q) for q in (u, v, w)), box, dt, nu, fx, return_pressure=True)
+    for got, want, name in zip((u1, v1, w1, p), ref, ("u", "v", "w", "p")):
+        e = rel(got.cpu().numpy(), want.numpy())
+        assert e <= 1e-12, f"{name}: rel-L2 {e:.3e}"
+    assert torch.all(v1[-1] == 0)
+    d = O.divergence(u1.cpu(), v1.cpu(), w1.cpu(), box)
+    d0 = O.divergence(*(torch.tensor(q) for q in (u, v, w)), box)
+    assert d.abs().max() <= 1e-12 * d0.abs().max()
+
+
+def test_projection_step_in_place_and_repeatable():
+    pl, box = setup(64, 32, 48, 2.0)
+    u, v, w = synth.perturbed_poiseuille(64, 32, 48, box.y_faces, seed=3)
+    a = [torch.tensor(q, device=dev()) for q in (u, v, w)]
+    b = [torch.tensor(q, device=dev()) for q in (u, v, w)]
+    ra = pl.projection_step(*a, 1e-3, 1 / 550, 3 / 550)
+    rb = pl.projection_step(*b, 1e-3, 1 / 550, 3 / 550, out=tuple(b))
+    for x, y in zip(ra, rb):
+        assert torch.equal(x, y)
+
+
+def test_step_needs_step_workspace():
+    from paper_2104_08863_amd.api import Plan
+    from paper_2104_08863_amd._lib import ChanflowError
+    yf = synth.tanh_faces(8, 2.0)
+    pl = Plan(16, 8, 8, 1.0, 1.0, yf)
+    z = torch.zeros(8, 8, 16, dtype=torch.float64, device=dev())
+    with pytest.raises(ChanflowError):
+        pl.projection_step(z, z, z, 1e-3, 0.01, 0.0)
+
+
+def test_full_size_step_properties():
+    """The 1024x256x512 step (the bench workload): the result is discretely
+    divergence-free and the top-wall v plane is zero; a second step from the
+    result keeps it so; two runs agree bitwise."""
+    wl = synth.WORKLOADS["step550"]
+    pl, box = setup(wl.nx, wl.ny, wl.nz, wl.gamma, wl.lx, wl.lz)
+    u, v, w = synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, box.y_faces, seed=0)
+    ug, vg, wg = (torch.tensor(q, device=dev()) for q in (u, v, w))
+    del u, v, w
+    u1, v1, w1 = pl.projection_step(ug, vg, wg, wl.dt, wl.nu, wl.fx)
+    u1b, v1b, w1b = pl.projection_step(ug, vg, wg, wl.dt, wl.nu, wl.fx)
+    assert torch.equal(u1, u1b) and torch.equal(v1, v1b) and torch.equal(w1, w1b)
+    d0 = pl.divergence(ug, vg, wg)
+    d1 = pl.divergence(u1, v1, w1)
+    assert float(d1.abs().max()) <= 1e-12 * float(d0.abs().max())
+    assert bool(torch.all(v1[-1] == 0))
+    u2, v2, w2 = pl.projection_step(u1, v1, w1, wl.dt, wl.nu, wl.fx)
+    d2 = pl.divergence(u2, v2, w2)
+    assert float(d2.abs().max()) <= 1e-12 * float(d0.abs().max())
