@@ -9,8 +9,8 @@
 //   stage 2: us = (u + ub)/2 + dt/2 R(ub)   (= u + dt/2 [R(u) + R(ub)])
 //   correction: u1 = us - dt G p
 //
-// One thread per grid point evaluates all three components at its (i, j, k);
-// neighbour values come through the caches.  Fields are (ny, nz, nx), x
+// The RK stages march in y over LDS-resident planes (2.5D tiling, see
+// k_rk_stage); the correction is pointwise.  Fields are (ny, nz, nx), x
 // fastest; v[ny-1] is the top wall (read as 0, written as 0).
 #pragma once
 
@@ -33,46 +33,33 @@ struct RhsOut {
   T ru, rv, rw;
 };
 
+// R at point (i, j, k) from an accessor A with A.u(dj, dk, di) etc. returning
+// the neighbour values (dj, dk, di in {-1, 0, 1}); A returns 0 for v on the
+// top wall and for planes outside [0, ny).
 template <typename T>
-__device__ __forceinline__ RhsOut<T> momentum_rhs(const T* __restrict__ u, const T* __restrict__ v,
-                                                  const T* __restrict__ w, const Geo<T>& g, int i,
-                                                  int j, int k, T nu, T fx) {
-  const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int ip = (i + 1 == nx) ? 0 : i + 1, im = (i == 0) ? nx - 1 : i - 1;
-  const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
-  const long pl = (long)nz * nx;
-  const long r0 = ((long)j * nz + k) * nx;         // row (j, k)
-  const long rkp = ((long)j * nz + kp) * nx;       // row (j, k+1)
-  const long rkm = ((long)j * nz + km) * nx;       // row (j, k-1)
+struct FaceFlux {
+  T exy, eyz;  // x-y and y-z edge products at the upper face of the cell
+};
+
+// `below`: the edge products at the lower face (j) when have_below (they are
+// the upper-face products of plane j-1); `above` receives those of face j+1.
+template <typename T, class Acc>
+__device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g, int j, T nu, T fx,
+                                                  bool have_below, FaceFlux<T> below, FaceFlux<T>& above) {
+  const int ny = g.ny;
   const bool top = (j == ny - 1), bot = (j == 0);
   const T h = T(0.5);
-  // ---- values
-  const T u0 = u[r0 + i], uip = u[r0 + ip], uim = u[r0 + im];
-  const T ukp = u[rkp + i], ukm = u[rkm + i], ukpm = u[rkp + im];
-  const T w0 = w[r0 + i], wip = w[r0 + ip], wim = w[r0 + im];
-  const T wkp = w[rkp + i], wkm = w[rkm + i], wkmp = w[rkm + ip];
-  const T v0 = top ? T(0) : v[r0 + i];
-  const T vip = top ? T(0) : v[r0 + ip], vim = top ? T(0) : v[r0 + im];
-  const T vkp = top ? T(0) : v[rkp + i], vkm = top ? T(0) : v[rkm + i];
-  T uj1 = T(0), uj1m = T(0), wj1 = T(0), wj1m = T(0), vj1 = T(0);
-  if (!top) {
-    uj1 = u[r0 + pl + i];
-    uj1m = u[r0 + pl + im];
-    wj1 = w[r0 + pl + i];
-    wj1m = w[rkm + pl + i];
-    vj1 = (j + 1 == ny - 1) ? T(0) : v[r0 + pl + i];
-  }
-  T ujm = T(0), wjm = T(0), vjm = T(0), vjmip = T(0), vjmkp = T(0);
-  if (!bot) {
-    ujm = u[r0 - pl + i];
-    wjm = w[r0 - pl + i];
-    vjm = v[r0 - pl + i];
-    vjmip = v[r0 - pl + ip];
-    vjmkp = v[rkp - pl + i];
-  }
+  const T u0 = A.u(0, 0, 0), uip = A.u(0, 0, 1), uim = A.u(0, 0, -1);
+  const T ukp = A.u(0, 1, 0), ukm = A.u(0, -1, 0), ukpm = A.u(0, 1, -1);
+  const T w0 = A.w(0, 0, 0), wip = A.w(0, 0, 1), wim = A.w(0, 0, -1);
+  const T wkp = A.w(0, 1, 0), wkm = A.w(0, -1, 0), wkmp = A.w(0, -1, 1);
+  const T v0 = A.v(0, 0, 0), vip = A.v(0, 0, 1), vim = A.v(0, 0, -1);
+  const T vkp = A.v(0, 1, 0), vkm = A.v(0, -1, 0);
+  const T uj1 = A.u(1, 0, 0), uj1m = A.u(1, 0, -1), wj1 = A.w(1, 0, 0), wj1m = A.w(1, -1, 0);
+  const T vj1 = A.v(1, 0, 0);
+  const T ujm = A.u(-1, 0, 0), wjm = A.w(-1, 0, 0), vjm = A.v(-1, 0, 0);
   const T rdy = g.rdy[j];
-  // ---- edge products (flux form)
-  // x-y edges at face j+1 (u interpolated in y, v in x), at i and i-1
+  // x-y and y-z edge products at face j+1 (u, w interpolated in y, v in x or z)
   T exy_i = T(0), exy_im = T(0), eyz_k = T(0), eyz_km = T(0);
   if (!top) {
     const T a = g.wl[j], b = g.wu[j];
@@ -81,35 +68,40 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const T* __restrict__ u, const
     eyz_k = (w0 * a + wj1 * b) * (h * (v0 + vkp));
     eyz_km = (wkm * a + wj1m * b) * (h * (vkm + v0));
   }
-  T exy_b = T(0), eyz_b = T(0);  // face j (bottom of cell j) at (k, i)
-  if (!bot) {
+  T exy_b = T(0), eyz_b = T(0);  // face j (bottom of cell j)
+  if (have_below) {
+    exy_b = below.exy;
+    eyz_b = below.eyz;
+  } else if (!bot) {
     const T a = g.wl[j - 1], b = g.wu[j - 1];
-    exy_b = (ujm * a + u0 * b) * (h * (vjm + vjmip));
-    eyz_b = (wjm * a + w0 * b) * (h * (vjm + vjmkp));
+    exy_b = (ujm * a + u0 * b) * (h * (vjm + A.v(-1, 0, 1)));
+    eyz_b = (wjm * a + w0 * b) * (h * (vjm + A.v(-1, 1, 0)));
   }
-  // x-z edges at (i+1/2, k+1/2) and neighbours
+  above.exy = exy_i;
+  above.eyz = eyz_k;
+  // x-z edge products at (i+1/2, k+1/2) and the neighbours
   const T exz = (h * (u0 + ukp)) * (h * (w0 + wip));
   const T exz_km = (h * (ukm + u0)) * (h * (wkm + wkmp));
   const T exz_im = (h * (uim + ukpm)) * (h * (wim + w0));
-  // ---- x-momentum
+  // x-momentum
   const T ucp = h * (uip + u0), ucm = h * (u0 + uim);
-  T nxu = (ucp * ucp - ucm * ucm) * g.rdx + (exy_i - exy_b) * rdy + (exz - exz_km) * g.rdz;
+  const T nxu = (ucp * ucp - ucm * ucm) * g.rdx + (exy_i - exy_b) * rdy + (exz - exz_km) * g.rdz;
   T lu = (uip - T(2) * u0 + uim) * g.rdx2 + (ukp - T(2) * u0 + ukm) * g.rdz2;
   {
     const T ft = top ? -T(2) * u0 * g.rdy[ny - 1] : (uj1 - u0) * g.rdyc[j];
     const T fb = bot ? T(2) * u0 * g.rdy[0] : (u0 - ujm) * g.rdyc[j - 1];
     lu += (ft - fb) * rdy;
   }
-  // ---- z-momentum
+  // z-momentum
   const T cwp = h * (wkp + w0), cwm = h * (w0 + wkm);
-  T nzw = (exz - exz_im) * g.rdx + (eyz_k - eyz_b) * rdy + (cwp * cwp - cwm * cwm) * g.rdz;
+  const T nzw = (exz - exz_im) * g.rdx + (eyz_k - eyz_b) * rdy + (cwp * cwp - cwm * cwm) * g.rdz;
   T lw = (wip - T(2) * w0 + wim) * g.rdx2 + (wkp - T(2) * w0 + wkm) * g.rdz2;
   {
     const T ft = top ? -T(2) * w0 * g.rdy[ny - 1] : (wj1 - w0) * g.rdyc[j];
     const T fb = bot ? T(2) * w0 * g.rdy[0] : (w0 - wjm) * g.rdyc[j - 1];
     lw += (ft - fb) * rdy;
   }
-  // ---- y-momentum (interior faces only)
+  // y-momentum (interior faces only)
   T rv = T(0);
   if (!top) {
     const T ct = h * (vj1 + v0), cb = h * (v0 + vjm);
@@ -125,31 +117,139 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const T* __restrict__ u, const
   return o;
 }
 
+// 2.5D tiling: a block owns TX x TZ columns (x, z) and marches over a chunk of
+// CY planes in y, keeping three consecutive planes of u, v, w (with a one-cell
+// halo in x and z, periodic wrap) in LDS; every field value is read from
+// global memory once per plane step plus the halo.
+template <int TX, int TZ, int CY>
+struct RkTile {
+  static constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, THREADS = TX * TZ;
+};
+
+template <typename T, int TX, int TZ>
+struct LdsAcc {
+  const T* su;  // three plane slots of u, each PLANE values
+  const T* sv;
+  const T* sw;
+  int sm, s0, sp;  // slot offsets of planes j-1, j, j+1
+  int base;        // (tz+1)*SX + tx+1
+  static constexpr int SX = TX + 2;
+  __device__ __forceinline__ int off(int dj, int dk, int di) const {
+    return (dj < 0 ? sm : (dj > 0 ? sp : s0)) + base + dk * SX + di;
+  }
+  __device__ __forceinline__ T u(int dj, int dk, int di) const { return su[off(dj, dk, di)]; }
+  __device__ __forceinline__ T v(int dj, int dk, int di) const { return sv[off(dj, dk, di)]; }
+  __device__ __forceinline__ T w(int dj, int dk, int di) const { return sw[off(dj, dk, di)]; }
+};
+
 // STAGE 1: out = f + dt R(f).  STAGE 2: out = (f0 + f)/2 + dt/2 R(f).
-template <typename T, int STAGE>
-__global__ void __launch_bounds__(256)
+// Plane j+2 is fetched into registers while plane j is computed from LDS.
+template <typename T, int STAGE, int TX, int TZ, int CY>
+__global__ void __launch_bounds__(TX * TZ)
 k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w,
            const T* u0, const T* v0, const T* w0, T* uo, T* vo, T* wo, Geo<T> g, T dt, T nu, T fx) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n) return;
-  const int i = int(id % g.nx);
-  const long jk = id / g.nx;
-  const int k = int(jk % g.nz);
-  const int j = int(jk / g.nz);
-  const RhsOut<T> r = momentum_rhs<T>(u, v, w, g, i, j, k, nu, fx);
-  const bool top = (j == g.ny - 1);
-  if (STAGE == 1) {
-    uo[id] = u[id] + dt * r.ru;
-    vo[id] = top ? T(0) : v[id] + dt * r.rv;
-    wo[id] = w[id] + dt * r.rw;
-  } else {
-    const T h = T(0.5), hd = T(0.5) * dt;
-    const T a = u0[id], b = top ? T(0) : v0[id], c = w0[id];
-    uo[id] = h * (a + u[id]) + hd * r.ru;
-    vo[id] = top ? T(0) : h * (b + v[id]) + hd * r.rv;
-    wo[id] = h * (c + w[id]) + hd * r.rw;
+  using Tl = RkTile<TX, TZ, CY>;
+  constexpr int PER = (Tl::PLANE + Tl::THREADS - 1) / Tl::THREADS;  // tile values per thread
+  __shared__ T su[3 * Tl::PLANE], sv[3 * Tl::PLANE], sw[3 * Tl::PLANE];
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
+  int b = blockIdx.x;
+  const int bx = b % ntx;
+  b /= ntx;
+  const int bz = b % ntz;
+  const int by = b / ntz;
+  const int i0 = bx * TX, k0 = bz * TZ;
+  const int j0 = by * CY, j1 = (j0 + CY < ny) ? j0 + CY : ny;
+  const int tx = threadIdx.x % TX, tz = threadIdx.x / TX;
+  const int i = i0 + tx, k = k0 + tz;
+  const bool mine = (i < nx) && (k < nz);
+  const long plane = (long)nx * nz;
+  // in-plane offsets of this thread's tile values (periodic wrap); -1 = none
+  int toff[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * Tl::THREADS;
+    const int zz = idx / Tl::SX, xx = idx % Tl::SX;
+    int gi = (i0 + xx - 1) % nx;
+    if (gi < 0) gi += nx;
+    int gk = (k0 + zz - 1) % nz;
+    if (gk < 0) gk += nz;
+    toff[q] = (idx < Tl::PLANE) ? gk * nx + gi : -1;
   }
+  T ru[PER], rv[PER], rw[PER];
+#define CF_RK_FETCH(jj)                                          \
+  _Pragma("unroll") for (int q = 0; q < PER; ++q) {             \
+    ru[q] = rv[q] = rw[q] = T(0);                               \
+    if (toff[q] >= 0 && (jj) >= 0 && (jj) < ny) {               \
+      const long o = (long)(jj) * plane + toff[q];              \
+      ru[q] = u[o];                                             \
+      rw[q] = w[o];                                             \
+      if ((jj) < ny - 1) rv[q] = v[o];                          \
+    }                                                           \
+  }
+#define CF_RK_STORE(s)                                           \
+  _Pragma("unroll") for (int q = 0; q < PER; ++q) {             \
+    if (toff[q] >= 0) {                                         \
+      const int idx = threadIdx.x + q * Tl::THREADS;            \
+      su[(s) * Tl::PLANE + idx] = ru[q];                        \
+      sv[(s) * Tl::PLANE + idx] = rv[q];                        \
+      sw[(s) * Tl::PLANE + idx] = rw[q];                        \
+    }                                                           \
+  }
+  const long pid = (long)k * nx + i;  // this thread's in-plane offset
+  CF_RK_FETCH(j0 - 1)
+  CF_RK_STORE((j0 + 2) % 3)
+  CF_RK_FETCH(j0)
+  CF_RK_STORE(j0 % 3)
+  CF_RK_FETCH(j0 + 1)
+  T a0 = T(0), b0 = T(0), c0 = T(0);
+  if (STAGE == 2 && mine) {
+    a0 = u0[(long)j0 * plane + pid];
+    b0 = (j0 < ny - 1) ? v0[(long)j0 * plane + pid] : T(0);
+    c0 = w0[(long)j0 * plane + pid];
+  }
+  LdsAcc<T, TX, TZ> A{su, sv, sw, 0, 0, 0, (tz + 1) * Tl::SX + tx + 1};
+  FaceFlux<T> carry{T(0), T(0)};
+  bool have = false;
+  for (int j = j0; j < j1; ++j) {
+    CF_RK_STORE((j + 1) % 3)
+    __syncthreads();
+    CF_RK_FETCH(j + 2)
+    T a1 = T(0), b1 = T(0), c1 = T(0);
+    if (STAGE == 2 && mine && j + 1 < j1) {
+      a1 = u0[(long)(j + 1) * plane + pid];
+      b1 = (j + 1 < ny - 1) ? v0[(long)(j + 1) * plane + pid] : T(0);
+      c1 = w0[(long)(j + 1) * plane + pid];
+    }
+    A.sm = ((j + 2) % 3) * Tl::PLANE;
+    A.s0 = (j % 3) * Tl::PLANE;
+    A.sp = ((j + 1) % 3) * Tl::PLANE;
+    if (mine) {
+      FaceFlux<T> up;
+      const RhsOut<T> r = momentum_rhs<T>(A, g, j, nu, fx, have, carry, up);
+      carry = up;
+      have = true;
+      const long id = (long)j * plane + pid;
+      const bool top = (j == ny - 1);
+      const T uc = A.u(0, 0, 0), vc = A.v(0, 0, 0), wc = A.w(0, 0, 0);
+      if (STAGE == 1) {
+        uo[id] = uc + dt * r.ru;
+        vo[id] = top ? T(0) : vc + dt * r.rv;
+        wo[id] = wc + dt * r.rw;
+      } else {
+        const T hh = T(0.5), hd = T(0.5) * dt;
+        uo[id] = hh * (a0 + uc) + hd * r.ru;
+        vo[id] = top ? T(0) : hh * (b0 + vc) + hd * r.rv;
+        wo[id] = hh * (c0 + wc) + hd * r.rw;
+      }
+    }
+    a0 = a1;
+    b0 = b1;
+    c0 = c1;
+    __syncthreads();
+  }
+#undef CF_RK_FETCH
+#undef CF_RK_STORE
 }
 
 // u1 = us - dt G p (in place on the velocity arrays); the top-wall v plane is 0.

@@ -4,19 +4,22 @@
 
 namespace cf {
 
+// Tile: 64 x 8 columns, chunks of 32 planes.
+constexpr int RK_TX = 64, RK_TZ = 8, RK_CY = 32;
+
 template <typename T>
 hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const T* u0, const T* v0,
                            const T* w0, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu, T fx,
                            hipStream_t s) {
-  const long n = (long)g.nx * g.ny * g.nz;
-  const int th = 256;
-  const long blocks = (n + th - 1) / th;
+  const long blocks = (long)((g.nx + RK_TX - 1) / RK_TX) * ((g.nz + RK_TZ - 1) / RK_TZ) *
+                      ((g.ny + RK_CY - 1) / RK_CY);
+  const dim3 th(RK_TX * RK_TZ);
   if (stage == 1)
-    hipLaunchKernelGGL((k_rk_stage<T, 1>), dim3(blocks), dim3(th), 0, s, u, v, w, u0, v0, w0, uo, vo, wo, g,
-                       dt, nu, fx);
+    hipLaunchKernelGGL((k_rk_stage<T, 1, RK_TX, RK_TZ, RK_CY>), dim3(blocks), th, 0, s, u, v, w, u0, v0, w0,
+                       uo, vo, wo, g, dt, nu, fx);
   else
-    hipLaunchKernelGGL((k_rk_stage<T, 2>), dim3(blocks), dim3(th), 0, s, u, v, w, u0, v0, w0, uo, vo, wo, g,
-                       dt, nu, fx);
+    hipLaunchKernelGGL((k_rk_stage<T, 2, RK_TX, RK_TZ, RK_CY>), dim3(blocks), th, 0, s, u, v, w, u0, v0, w0,
+                       uo, vo, wo, g, dt, nu, fx);
   return hipGetLastError();
 }
 
