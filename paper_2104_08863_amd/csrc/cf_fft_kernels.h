@@ -178,6 +178,59 @@ struct SrcDiv {
   }
 };
 
+// FP64 residual of the Poisson equation, r = f - L_h p (7-point staggered
+// Laplacian, no flux through the walls: a_0 = c_{ny-1} = 0), rounded to T.
+// f may be given directly or, when u != nullptr, as scale * D(u, v, w).
+template <typename T, typename Ts>
+struct SrcResidual {
+  const double* __restrict__ f;
+  const Ts* __restrict__ u;
+  const Ts* __restrict__ v;
+  const Ts* __restrict__ w;
+  const double* __restrict__ p;
+  const double* __restrict__ a;
+  const double* __restrict__ c;
+  const double* __restrict__ rdy;
+  double rdx, rdz, rdx2, rdz2, scale;
+  int nx, ny, nz;
+  __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
+    const long plane = (long)nz * nx;
+    const long row = ((long)j * nz + k) * nx;
+    const int kp = (k + 1 == nz) ? 0 : k + 1, km = (k == 0) ? nz - 1 : k - 1;
+    const long rowp = ((long)j * nz + kp) * nx, rowm = ((long)j * nz + km) * nx;
+    const int i0 = 2 * m, i1 = 2 * m + 1;
+    const int im = (m == 0) ? nx - 1 : i0 - 1, ip = (i1 + 1 == nx) ? 0 : i1 + 1;
+    double f0, f1;
+    if (u) {
+      SrcDiv<double, Ts> d{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz};
+      const cx<double> fd = d.pair(j, k, m);
+      f0 = fd.re;
+      f1 = fd.im;
+    } else {
+      const cx<double> fp = reinterpret_cast<const cx<double>*>(f + row)[m];
+      f0 = fp.re;
+      f1 = fp.im;
+    }
+    const cx<double> pc = reinterpret_cast<const cx<double>*>(p + row)[m];
+    const double pim = p[row + im], pip = p[row + ip];
+    const cx<double> pkp = reinterpret_cast<const cx<double>*>(p + rowp)[m];
+    const cx<double> pkm = reinterpret_cast<const cx<double>*>(p + rowm)[m];
+    double l0 = (pc.im - 2.0 * pc.re + pim) * rdx2 + (pkp.re - 2.0 * pc.re + pkm.re) * rdz2;
+    double l1 = (pip - 2.0 * pc.im + pc.re) * rdx2 + (pkp.im - 2.0 * pc.im + pkm.im) * rdz2;
+    if (j + 1 < ny) {
+      const cx<double> q = reinterpret_cast<const cx<double>*>(p + row + plane)[m];
+      l0 += c[j] * (q.re - pc.re);
+      l1 += c[j] * (q.im - pc.im);
+    }
+    if (j > 0) {
+      const cx<double> q = reinterpret_cast<const cx<double>*>(p + row - plane)[m];
+      l0 += a[j] * (q.re - pc.re);
+      l1 += a[j] * (q.im - pc.im);
+    }
+    return mk(T(f0 - l0), T(f1 - l1));
+  }
+};
+
 template <typename T, int NH, typename Src>
 __global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
 k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ twp,
@@ -236,6 +289,20 @@ struct DstPlain {
   __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
     cx<Tout>* row = reinterpret_cast<cx<Tout>*>(p + ((long)j * nz + k) * nx);
     row[m] = mk(Tout(v.re), Tout(v.im));
+  }
+};
+
+// p += correction (iterative refinement: the correction solve adds to p).
+template <typename T>
+struct DstAccum {
+  double* __restrict__ p;
+  int nx, nz;
+  __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
+    cx<double>* row = reinterpret_cast<cx<double>*>(p + ((long)j * nz + k) * nx);
+    cx<double> o = row[m];
+    o.re += double(v.re);
+    o.im += double(v.im);
+    row[m] = o;
   }
 };
 

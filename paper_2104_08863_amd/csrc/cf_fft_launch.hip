@@ -88,6 +88,39 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
   }
 }
 
+template <typename T, typename Ts>
+hipError_t launch_r2c_resid(int nh, const double* f, const Ts* u, const Ts* v, const Ts* w, double scale,
+                            const double* p, const double* a, const double* c, const double* rdy,
+                            double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, hipStream_t s) {
+  SrcResidual<T, Ts> src{f, u, v, w, p, a, c, rdy, rdx, rdz, rdx * rdx, rdz * rdz, scale, 2 * nh, ny, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return r2c_n<T, N>(src, spec, tw, twp, ny, nz, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, typename Ts>
+hipError_t launch_r2c_div_t(int nh, const Ts* u, const Ts* v, const Ts* w, const double* rdy, double rdx,
+                            double rdz, double scale, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
+                            int nz, hipStream_t s) {
+  SrcDiv<T, Ts> src{u, v, w, rdy, rdx, rdz, scale, 2 * nh, ny, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return r2c_n<T, N>(src, spec, tw, twp, ny, nz, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template <typename T, int NH, typename Dst>
 static hipError_t c2r_n(const cx<T>* spec, Dst dst, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
                         T scale, hipStream_t s) {
@@ -113,6 +146,37 @@ hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* t
       return hipErrorInvalidValue;
   }
 }
+
+template <typename T>
+hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
+                            int nz, T scale, hipStream_t s) {
+  DstAccum<T> dst{p, 2 * nh, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return c2r_n<T, N>(spec, dst, tw, twp, ny, nz, scale, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template hipError_t launch_r2c_resid<float, double>(int, const double*, const double*, const double*,
+                                                    const double*, double, const double*, const double*,
+                                                    const double*, const double*, double, double,
+                                                    cx<float>*, const cx<float>*, const cx<float>*, int, int,
+                                                    hipStream_t);
+template hipError_t launch_r2c_resid<float, float>(int, const double*, const float*, const float*,
+                                                   const float*, double, const double*, const double*,
+                                                   const double*, const double*, double, double,
+                                                   cx<float>*, const cx<float>*, const cx<float>*, int, int,
+                                                   hipStream_t);
+template hipError_t launch_r2c_div_t<float, float>(int, const float*, const float*, const float*,
+                                                   const double*, double, double, double, cx<float>*,
+                                                   const cx<float>*, const cx<float>*, int, int, hipStream_t);
+template hipError_t launch_c2r_accum<float>(int, const cx<float>*, double*, const cx<float>*,
+                                            const cx<float>*, int, int, float, hipStream_t);
 
 #define CF_INST(T)                                                                                   \
   template hipError_t launch_fft_z<T>(int, bool, const cx<T>*, cx<T>*, const cx<T>*, int, int, hipStream_t); \

@@ -28,6 +28,25 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
                           const double* rdy, double rdx, double rdz, double scale, cx<T>* spec,
                           const cx<T>* tw, const cx<T>* twp, int ny, int nz, hipStream_t s);
 
+// Forward real transform of the FP64 residual f - L_h p, with f given or (u
+// non-null) f = scale * D(u, v, w).
+template <typename T, typename Ts>
+hipError_t launch_r2c_resid(int nh, const double* f, const Ts* u, const Ts* v, const Ts* w, double scale,
+                            const double* p, const double* a, const double* c, const double* rdy,
+                            double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
+                            int ny, int nz, hipStream_t s);
+
+// Divergence fused into the forward real transform, velocity type Ts.
+template <typename T, typename Ts>
+hipError_t launch_r2c_div_t(int nh, const Ts* u, const Ts* v, const Ts* w, const double* rdy, double rdx,
+                            double rdz, double scale, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
+                            int nz, hipStream_t s);
+
+// Inverse real transform added into p (refinement correction).
+template <typename T>
+hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
+                            int nz, T scale, hipStream_t s);
+
 template <typename T>
 hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp,
                             int ny, int nz, T scale, hipStream_t s);

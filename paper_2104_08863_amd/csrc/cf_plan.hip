@@ -85,6 +85,7 @@ struct cf_plan {
   // projection-step workspace: RK stage-1 fields (state precision) and pressure
   void *ub = nullptr, *vb = nullptr, *wb = nullptr;
   double* pws = nullptr;
+  double* fws = nullptr;  // mixed precision: copy of f when p aliases it
   cf::Geo<double> g64{};
   cf::Geo<float> g32{};
 
@@ -361,6 +362,77 @@ cf_status poisson_t(cf_plan* pl, const double* f, double* p, hipStream_t s) {
   return CF_OK;
 }
 
+// Mixed-precision Poisson solve: p0 = S32(f), then refine_passes times
+// p += S32(f - L_h p) with the residual formed in FP64.  S32 runs the transforms
+// and the bulk PDD in FP32 and the FP64 line set in FP64.  When `u` is
+// non-null the right-hand side is scale * D(u, v, w) (float velocities).
+cf_status poisson_mixed(cf_plan* pl, const double* f, const float* u, const float* v, const float* w,
+                        double scale, double* p, hipStream_t s) {
+  using TB = Tabs<float>;
+  cx<float>* A = static_cast<cx<float>*>(pl->specA);
+  cx<float>* B = static_cast<cx<float>*>(pl->specB);
+  const double* fsrc = f;
+  if (!u && f == p && pl->opt.refine_passes > 0) {
+    CF_HIP(hipMemcpyAsync(pl->fws, f, sizeof(double) * (size_t)pl->nx * pl->ny * pl->nz,
+                          hipMemcpyDeviceToDevice, s),
+           "hipMemcpyAsync");
+    fsrc = pl->fws;
+  }
+  if (u) {
+    CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+div launch", [&] {
+      return cf::launch_r2c_div_t<float, float>(pl->nh, u, v, w, pl->d_rdy, 1.0 / pl->dx, 1.0 / pl->dz, scale, A,
+                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+    }));
+    CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+      return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
+    }));
+  } else {
+    CF_TRY(forward_t<float>(pl, fsrc, B, s));
+  }
+  CF_TRY(solve_t<float>(pl, B, B, s));
+  CF_TRY(inverse_t<float>(pl, B, p, s));
+  const float scl = float(1.0 / ((double)pl->nx * (double)pl->nz));
+  for (int it = 0; it < pl->opt.refine_passes; ++it) {
+    CF_TRY(timed(pl, CF_K_R2C_X, s, "residual r2c launch", [&] {
+      return cf::launch_r2c_resid<float, float>(pl->nh, fsrc, u, v, w, scale, p, pl->d_a, pl->d_c, pl->d_rdy,
+                                                1.0 / pl->dx, 1.0 / pl->dz, A, TB::twx(pl), TB::twp(pl),
+                                                pl->ny, pl->nz, s);
+    }));
+    CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+      return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
+    }));
+    CF_TRY(solve_t<float>(pl, B, B, s));
+    CF_TRY(timed(pl, CF_K_FFT_Z_INV, s, "z ifft launch", [&] {
+      return cf::launch_fft_z<float>(pl->nz, true, B, A, TB::twz(pl), pl->nkx, pl->ny, s);
+    }));
+    CF_TRY(timed(pl, CF_K_C2R_X, s, "c2r accumulate launch", [&] {
+      return cf::launch_c2r_accum<float>(pl->nh, A, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scl, s);
+    }));
+  }
+  return CF_OK;
+}
+
+// One mixed-precision projection step (FP32 velocity state, FP64 pressure).
+cf_status step_mixed(cf_plan* pl, const float* u, const float* v, const float* w, float* u1, float* v1,
+                     float* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
+  float* ub = static_cast<float*>(pl->ub);
+  float* vb = static_cast<float*>(pl->vb);
+  float* wb = static_cast<float*>(pl->wb);
+  double* pp = p ? p : pl->pws;
+  const float fdt = float(dt), fnu = float(nu), ffx = float(fx);
+  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
+    return cf::launch_rk_stage<float>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g32, fdt, fnu, ffx, s);
+  }));
+  CF_TRY(timed(pl, CF_K_RK2, s, "rk stage 2", [&] {
+    return cf::launch_rk_stage<float>(2, ub, vb, wb, u, v, w, u1, v1, w1, pl->g32, fdt, fnu, ffx, s);
+  }));
+  CF_TRY(poisson_mixed(pl, nullptr, u1, v1, w1, 1.0 / dt, pp, s));
+  CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
+    return cf::launch_correct<float>(u1, v1, w1, pp, pl->g32, fdt, s);
+  }));
+  return CF_OK;
+}
+
 // One FP64 projection step.
 cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w, double* u1, double* v1,
                  double* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
@@ -617,6 +689,9 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     pl->g32 = cf::Geo<float>{pl->s_rdy, pl->s_rdyc, pl->s_wl, pl->s_wu, (float)rdx, (float)rdz,
                              (float)(rdx * rdx), (float)(rdz * rdz), nx, ny, nz};
   }
+  if (opt.precision == CF_MIXED && opt.refine_passes > 0) {
+    if ((st = dalloc(pl, &pl->fws, (size_t)nx * ny * nz)) != CF_OK) return bail(st);
+  }
   if (opt.flags & CF_PLAN_STEP) {
     const size_t npts = (size_t)nx * ny * nz;
     if (opt.precision == CF_FP64) {
@@ -720,7 +795,7 @@ cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream
   CF_TRY(check_ptr(f, "f"));
   CF_TRY(check_ptr(p, "p"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (pl->mixed()) return poisson_t<float>(pl, f, p, s);
+  if (pl->mixed()) return poisson_mixed(pl, f, nullptr, nullptr, nullptr, 1.0, p, s);
   return poisson_t<double>(pl, f, p, s);
 }
 
@@ -753,7 +828,9 @@ cf_status cf_projection_step(cf_plan* pl, const void* u, const void* v, const vo
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
   if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (pl->mixed()) return fail(CF_ERR_UNSUPPORTED, "mixed-precision projection step is not built yet");
+  if (pl->mixed())
+    return step_mixed(pl, static_cast<const float*>(u), static_cast<const float*>(v), static_cast<const float*>(w),
+                      static_cast<float*>(u1), static_cast<float*>(v1), static_cast<float*>(w1), p, dt, nu, fx, s);
   return step64(pl, static_cast<const double*>(u), static_cast<const double*>(v), static_cast<const double*>(w),
                 static_cast<double*>(u1), static_cast<double*>(v1), static_cast<double*>(w1), p, dt, nu, fx, s);
 }

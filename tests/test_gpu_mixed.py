@@ -1,0 +1,87 @@
+"""Mixed precision (FP32 transforms and bulk PDD, FP64 low-wavenumber lines, FP64
+residual + refinement) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def plans(nx, ny, nz, gamma, lx, lz, **kw):
+    from paper_2104_08863_amd.api import Plan
+    yf = synth.tanh_faces(ny, gamma)
+    return yf, O.Box(nx, ny, nz, lx, lz, yf), lambda r: Plan(nx, ny, nz, lx, lz, yf, precision="mixed",
+                                                            refine_passes=r, **kw)
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma", [(64, 64, 64, 2.0), (256, 128, 192, 2.6), (96, 48, 24, 2.5)])
+def test_mixed_poisson_refinement(nx, ny, nz, gamma):
+    """RHS = divergence of a seeded field with a k^-5/3-like horizontal spectrum
+    (the mixed-precision workload's recipe).  One FP64 residual + correction
+    pass brings the FP32-bulk solution to <= 1e-6 rel-L2 of the FP64 oracle."""
+    yf, box, mk = plans(nx, ny, nz, gamma, 4 * np.pi, 2 * np.pi)
+    u, v, w = synth.powerlaw_velocity(nx, ny, nz, seed=0)
+    f = O.divergence(*(torch.tensor(q) for q in (u, v, w)), box)
+    f = f - O.mean_w(f, box)
+    ref = O.poisson(f, box).numpy()
+    fg = torch.tensor(f.numpy(), device=dev())
+    errs = []
+    for r in (0, 1, 2):
+        p = mk(r).poisson_solve(fg).cpu().numpy()
+        errs.append(rel(p, ref))
+    print(f"mixed {nx}x{ny}x{nz}: rel-L2 p0 {errs[0]:.3e}, p1 {errs[1]:.3e}, p2 {errs[2]:.3e}")
+    assert errs[0] < 1e-3
+    assert errs[1] <= 1e-6
+    assert errs[1] < errs[0] and errs[2] <= errs[1] * 1.5
+
+
+def test_mixed_poisson_alias_and_fp64_lines():
+    nx, ny, nz = 64, 32, 48
+    yf, box, mk = plans(nx, ny, nz, 2.0, 2 * np.pi, np.pi)
+    pl = mk(1)
+    info = pl.info()
+    assert info["n_special"] == 4 * 7   # kx < 4 and min(kz, nz - kz) < 4
+    f = torch.tensor(synth.uniform_rhs(nx, ny, nz, seed=2), device=dev())
+    p = pl.poisson_solve(f.clone())
+    g = f.clone()
+    pl.poisson_solve(g, out=g)
+    assert torch.equal(p, g)
+    ref = O.poisson(torch.tensor(f.cpu().numpy()), box).numpy()
+    assert rel(p.cpu().numpy(), ref) <= 1e-6
+
+
+def test_mixed_projection_step():
+    """FP32 velocity state: the step agrees with the FP64 oracle to FP32 storage
+    accuracy and its divergence falls by many orders of magnitude."""
+    from paper_2104_08863_amd.api import Plan
+    nx, ny, nz, gamma = 64, 48, 32, 2.0
+    yf = synth.tanh_faces(ny, gamma)
+    box = O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+    pl = Plan(nx, ny, nz, 2 * np.pi, np.pi, yf, precision="mixed", step=True)
+    dt, nu = 1e-3, 1 / 550
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, yf, seed=0)
+    ug, vg, wg = (torch.tensor(q, dtype=torch.float32, device=dev()) for q in (u, v, w))
+    p = torch.empty(ny, nz, nx, dtype=torch.float64, device=dev())
+    u1, v1, w1 = pl.projection_step(ug, vg, wg, dt, nu, 3 * nu, p=p)
+    ins = [torch.tensor(q.cpu().numpy(), dtype=torch.float64) for q in (ug, vg, wg)]
+    ref = O.projection_step(*ins, box, dt, nu, 3 * nu, return_pressure=True)
+    for got, want, name in zip((u1, v1, w1), ref[:3], "uvw"):
+        e = rel(got.cpu().double().numpy(), want.numpy())
+        assert e <= 2e-6, f"{name}: {e:.3e}"
+    ep = rel(p.cpu().numpy(), ref[3].numpy())
+    assert ep <= 1e-5, ep
+    d1 = O.divergence(*(q.cpu().double() for q in (u1, v1, w1)), box)
+    d0 = O.divergence(*ins, box)
+    assert d1.abs().max() <= 1e-5 * d0.abs().max()
+    assert bool(torch.all(v1[-1] == 0))
