@@ -65,10 +65,11 @@ typedef struct {
   int fp64_kx;        /* CF_MIXED: lines with kx < fp64_kx and min(kz, nz-kz) < fp64_kz */
   int fp64_kz;        /*   are solved in FP64 (default 4, 4) */
   int refine_passes;  /* CF_MIXED: FP64 residual + correction solves (default 1) */
-  int flags;          /* CF_PLAN_STEP: also allocate the projection-step workspace */
+  int flags;          /* CF_PLAN_STEP: allocate the projection-step workspace;
+                         CF_PLAN_ADJOINT: also the workspace of its adjoint */
 } cf_options;
 
-enum { CF_PLAN_STEP = 1 };
+enum { CF_PLAN_STEP = 1, CF_PLAN_ADJOINT = 2 };
 
 typedef struct {
   int nx, ny, nz, precision;
@@ -136,6 +137,29 @@ cf_status cf_projection_step(cf_plan* plan, const void* u, const void* v, const 
                              void* v1, void* w1, double* p, double dt, double nu, double fx,
                              void* stream);
 
+/*
+ * Adjoint of cf_projection_step (the differentiated form of Section 2, Eq. (3)-(7)):
+ * given the step input (u, v, w) and g1 = dJ/d(u1, v1, w1), returns
+ * g = dJ/d(u, v, w) (Euclidean gradient, what autograd expects), with
+ *   g* = P^T g1 = W P W^-1 g1          (P = I - G L_h^+ D; W = face volumes: the
+ *                                         pressure solve is self-adjoint in the
+ *                                         face-volume inner product),
+ *   gb = dt/2 J_R(ub)^T g*,  ub = u + dt R(u)   (recomputed),
+ *   g  = g* + gb + J_R(u)^T (dt/2 g* + dt gb).
+ * Entries of the top-wall v plane are not variables: their gradient is 0.
+ * g may alias g1 but not (u, v, w).  Arrays as in cf_projection_step.  The plan
+ * must have been created with CF_PLAN_STEP | CF_PLAN_ADJOINT.
+ */
+cf_status cf_projection_step_adjoint(cf_plan* plan, const void* u, const void* v, const void* w,
+                                     const void* gu1, const void* gv1, const void* gw1, void* gu,
+                                     void* gv, void* gw, double dt, double nu, double fx, void* stream);
+
+/* Test hook: (gu, gv, gw) = J_R(u, v, w)^T (lu, lv, lw), the transpose of the momentum
+ * right-hand side's Jacobian at (u, v, w).  Arrays as in cf_projection_step. */
+cf_status cf_rhs_adjoint(cf_plan* plan, const void* u, const void* v, const void* w, const void* lu,
+                         const void* lv, const void* lw, void* gu, void* gv, void* gw, double nu,
+                         void* stream);
+
 /* Test hook, steps (2)-(4): forward real transform in x then complex transform in z of f
  * (device double (ny, nz, nx)) into fhat (device complex, plan precision: double pairs
  * for CF_FP64, float pairs for CF_MIXED; shape (nx/2+1, ny, nz)). */
@@ -167,7 +191,9 @@ enum {
   CF_K_RK1 = 7,       /* RK2 stage 1 (momentum RHS) */
   CF_K_RK2 = 8,       /* RK2 stage 2 (momentum RHS) */
   CF_K_CORRECT = 9,   /* pressure-gradient correction u1 = u* - dt G p */
-  CF_K_COUNT = 10
+  CF_K_ADJ_RHS = 10,  /* transposed momentum right-hand side */
+  CF_K_ADJ_CORRECT = 11, /* weighted correction of the transposed projection */
+  CF_K_COUNT = 12
 };
 cf_status cf_plan_set_timing(cf_plan* plan, int enable);
 cf_status cf_plan_reset_timing(cf_plan* plan);

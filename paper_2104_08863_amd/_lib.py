@@ -16,8 +16,8 @@ HOSTLIB_PATH = os.path.join(PKG, "libchanflow_host.so")
 CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMERIC = range(6)
 CF_FP64, CF_MIXED = 0, 1
 KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
-           "rk_stage1", "rk_stage2", "correct"]
-CF_PLAN_STEP = 1
+           "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted"]
+CF_PLAN_STEP, CF_PLAN_ADJOINT = 1, 2
 
 
 class cf_options(C.Structure):
@@ -46,6 +46,8 @@ SIGNATURES = {
     "cf_poisson_solve": (_I, [_P, _P, _P, _P]),
     "cf_divergence": (_I, [_P, _P, _P, _P, _P, _D, _P]),
     "cf_projection_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
+    "cf_projection_step_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
+    "cf_rhs_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _P]),
     "cf_forward_spectral": (_I, [_P, _P, _P, _P]),
     "cf_inverse_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral": (_I, [_P, _P, _P, _P]),

@@ -25,7 +25,7 @@ class Plan:
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
                  precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
                  fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
-                 step: bool = False, device=None):
+                 step: bool = False, adjoint: bool = False, device=None):
         lib = L.lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nkx = self.nx // 2 + 1
@@ -45,7 +45,7 @@ class Plan:
         opt.fp64_kx = int(fp64_kx)
         opt.fp64_kz = int(fp64_kz)
         opt.refine_passes = int(refine_passes)
-        opt.flags = L.CF_PLAN_STEP if step else 0
+        opt.flags = (L.CF_PLAN_STEP if (step or adjoint) else 0) | (L.CF_PLAN_ADJOINT if adjoint else 0)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -152,6 +152,31 @@ class Plan:
         L.check(L.lib().cf_projection_step(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out[0]), _ptr(out[1]),
                                            _ptr(out[2]), pp, float(dt), float(nu), float(fx), _stream()),
                 "cf_projection_step")
+        return out
+
+    def projection_step_adjoint(self, u, v, w, gu1, gv1, gw1, dt: float, nu: float, fx: float, out=None):
+        """dJ/d(u, v, w) of one projection step from dJ/d(u1, v1, w1)."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w"), (gu1, "gu1"), (gv1, "gv1"), (gw1, "gw1")):
+            self._field(t, n, sd)
+        if out is None:
+            out = (self._new(sd), self._new(sd), self._new(sd))
+        for t, n in zip(out, ("gu", "gv", "gw")):
+            self._field(t, n, sd)
+        L.check(L.lib().cf_projection_step_adjoint(
+            self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(gu1), _ptr(gv1), _ptr(gw1), _ptr(out[0]), _ptr(out[1]),
+            _ptr(out[2]), float(dt), float(nu), float(fx), _stream()), "cf_projection_step_adjoint")
+        return out
+
+    def rhs_adjoint(self, u, v, w, lu, lv, lw, nu: float):
+        """J_R(u, v, w)^T (lu, lv, lw) (test hook)."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w"), (lu, "lu"), (lv, "lv"), (lw, "lw")):
+            self._field(t, n, sd)
+        out = (self._new(sd), self._new(sd), self._new(sd))
+        L.check(L.lib().cf_rhs_adjoint(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(lu), _ptr(lv), _ptr(lw),
+                                       _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), float(nu), _stream()),
+                "cf_rhs_adjoint")
         return out
 
     def forward_spectral(self, f: torch.Tensor, out=None) -> torch.Tensor:

@@ -1,0 +1,39 @@
+// Launch of the adjoint (transpose) kernels of the projection step.
+#include "cf_adjoint_kernels.h"
+#include "cf_internal.h"
+
+namespace cf {
+
+template <typename T>
+hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
+                              const T* bu, const T* bv, const T* bw, T c1, T c2, const AdjGeo<T>& g, T nu, T s,
+                              int add, T* gu, T* gv, T* gw, hipStream_t st) {
+  AdjAcc<T> X{u, v, w, au, av, aw, bu, bv, bw, c1, c2, g.g.nx, g.g.ny, g.g.nz};
+  const long n = (long)g.g.nx * g.g.ny * g.g.nz;
+  const int th = 256;
+  const long blocks = (n + th - 1) / th;
+  hipLaunchKernelGGL((k_rhs_adjoint<T>), dim3(blocks), dim3(th), 0, st, X, g, nu, s, add, gu, gv, gw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_correct_w(const T* gu, const T* gv, const T* gw, T* ou, T* ov, T* ow, const double* phi,
+                            const AdjGeo<T>& g, hipStream_t st) {
+  const long n = (long)g.g.nx * g.g.ny * g.g.nz;
+  const int th = 256;
+  const long blocks = (n + th - 1) / th;
+  hipLaunchKernelGGL((k_correct_w<T>), dim3(blocks), dim3(th), 0, st, gu, gv, gw, ou, ov, ow, phi, g);
+  return hipGetLastError();
+}
+
+#define CF_INST(T)                                                                                         \
+  template hipError_t launch_rhs_adjoint<T>(const T*, const T*, const T*, const T*, const T*, const T*,    \
+                                            const T*, const T*, const T*, T, T, const AdjGeo<T>&, T, T, int, \
+                                            T*, T*, T*, hipStream_t);                                      \
+  template hipError_t launch_correct_w<T>(const T*, const T*, const T*, T*, T*, T*, const double*,         \
+                                          const AdjGeo<T>&, hipStream_t);
+CF_INST(double)
+CF_INST(float)
+#undef CF_INST
+
+}  // namespace cf

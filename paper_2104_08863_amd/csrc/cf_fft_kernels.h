@@ -178,6 +178,46 @@ struct SrcDiv {
   }
 };
 
+// Divergence of the face field (g_u / dy_j, g_v / dyc_j, g_w / dy_j): the right-
+// hand side of the transposed projection (g / W with the face weights W).
+template <typename T, typename Ts>
+struct SrcDivW {
+  const Ts* __restrict__ u;
+  const Ts* __restrict__ v;
+  const Ts* __restrict__ w;
+  const double* __restrict__ rdy;
+  const double* __restrict__ rdyc;
+  double rdx, rdz;
+  int nx, ny, nz;
+  __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
+    const long row = ((long)j * nz + k) * nx;
+    const long plane = (long)nz * nx;
+    const int km = (k == 0) ? nz - 1 : k - 1;
+    const long rowm = ((long)j * nz + km) * nx;
+    const int im = (m == 0) ? nx - 1 : 2 * m - 1;
+    const double ry = rdy[j];
+    const cx<Ts> up = reinterpret_cast<const cx<Ts>*>(u + row)[m];
+    const double uim = double(u[row + im]);
+    const cx<Ts> wp = reinterpret_cast<const cx<Ts>*>(w + row)[m];
+    const cx<Ts> wmp = reinterpret_cast<const cx<Ts>*>(w + rowm)[m];
+    double v0 = 0.0, v1 = 0.0, vm0 = 0.0, vm1 = 0.0;
+    if (j < ny - 1) {
+      const cx<Ts> vp = reinterpret_cast<const cx<Ts>*>(v + row)[m];
+      v0 = double(vp.re) * rdyc[j];
+      v1 = double(vp.im) * rdyc[j];
+    }
+    if (j > 0) {
+      const cx<Ts> vmp = reinterpret_cast<const cx<Ts>*>(v + row - plane)[m];
+      vm0 = double(vmp.re) * rdyc[j - 1];
+      vm1 = double(vmp.im) * rdyc[j - 1];
+    }
+    const double f0 = ((double(up.re) - uim) * ry * rdx + (v0 - vm0) * ry + (double(wp.re) - double(wmp.re)) * ry * rdz);
+    const double f1 = ((double(up.im) - double(up.re)) * ry * rdx + (v1 - vm1) * ry +
+                       (double(wp.im) - double(wmp.im)) * ry * rdz);
+    return mk(T(f0), T(f1));
+  }
+};
+
 // FP64 residual of the Poisson equation, r = f - L_h p (7-point staggered
 // Laplacian, no flux through the walls: a_0 = c_{ny-1} = 0), rounded to T.
 // f may be given directly or, when u != nullptr, as scale * D(u, v, w).

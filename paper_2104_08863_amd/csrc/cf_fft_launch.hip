@@ -147,6 +147,25 @@ hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* t
   }
 }
 
+template <typename T, typename Ts>
+hipError_t launch_r2c_divw(int nh, const Ts* u, const Ts* v, const Ts* w, const double* rdy, const double* rdyc,
+                           double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
+                           int nz, hipStream_t s) {
+  SrcDivW<T, Ts> src{u, v, w, rdy, rdyc, rdx, rdz, 2 * nh, ny, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return r2c_n<T, N>(src, spec, tw, twp, ny, nz, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_r2c_divw<double, double>(int, const double*, const double*, const double*,
+                                                    const double*, const double*, double, double, cx<double>*,
+                                                    const cx<double>*, const cx<double>*, int, int, hipStream_t);
+
 template <typename T>
 hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
                             int nz, T scale, hipStream_t s) {

@@ -42,6 +42,28 @@ hipError_t launch_r2c_div_t(int nh, const Ts* u, const Ts* v, const Ts* w, const
                             double rdz, double scale, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
                             int nz, hipStream_t s);
 
+// Forward real transform of D(g / W) (transposed projection right-hand side).
+template <typename T, typename Ts>
+hipError_t launch_r2c_divw(int nh, const Ts* u, const Ts* v, const Ts* w, const double* rdy, const double* rdyc,
+                           double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
+                           int nz, hipStream_t s);
+
+template <typename T>
+struct AdjAcc;
+template <typename T>
+struct AdjGeo;
+
+// out = s * J_R(state)^T lam (+ A + B when add), lam = c1 A + c2 B (B may be null).
+template <typename T>
+hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
+                              const T* bu, const T* bv, const T* bw, T c1, T c2, const AdjGeo<T>& g, T nu, T s,
+                              int add, T* gu, T* gv, T* gw, hipStream_t st);
+
+// g* = g - W G phi.
+template <typename T>
+hipError_t launch_correct_w(const T* gu, const T* gv, const T* gw, T* ou, T* ov, T* ow, const double* phi,
+                            const AdjGeo<T>& g, hipStream_t st);
+
 // Inverse real transform added into p (refinement correction).
 template <typename T>
 hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,

@@ -19,6 +19,7 @@
 #include "cf_fft.h"
 #include "cf_internal.h"
 #include "cf_pdd.h"
+#include "cf_adjoint_kernels.h"
 #include "cf_step_kernels.h"
 
 namespace cf {
@@ -86,6 +87,12 @@ struct cf_plan {
   void *ub = nullptr, *vb = nullptr, *wb = nullptr;
   double* pws = nullptr;
   double* fws = nullptr;  // mixed precision: copy of f when p aliases it
+  // adjoint workspace: projected gradient g* and gb (state precision)
+  void *gsu = nullptr, *gsv = nullptr, *gsw = nullptr, *gbu = nullptr, *gbv = nullptr, *gbw = nullptr;
+  double *d_dyc = nullptr;
+  float *s_dy = nullptr, *s_dyc = nullptr;
+  cf::AdjGeo<double> a64{};
+  cf::AdjGeo<float> a32{};
   cf::Geo<double> g64{};
   cf::Geo<float> g32{};
 
@@ -456,6 +463,51 @@ cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w,
   return CF_OK;
 }
 
+// Adjoint of one FP64 projection step.
+cf_status step_adjoint64(cf_plan* pl, const double* u, const double* v, const double* w, const double* g1u,
+                         const double* g1v, const double* g1w, double* gu, double* gv, double* gw, double dt,
+                         double nu, double fx, hipStream_t s) {
+  double* ub = static_cast<double*>(pl->ub);
+  double* vb = static_cast<double*>(pl->vb);
+  double* wb = static_cast<double*>(pl->wb);
+  double* su = static_cast<double*>(pl->gsu);
+  double* sv = static_cast<double*>(pl->gsv);
+  double* sw = static_cast<double*>(pl->gsw);
+  double* bu = static_cast<double*>(pl->gbu);
+  double* bv = static_cast<double*>(pl->gbv);
+  double* bw = static_cast<double*>(pl->gbw);
+  // recompute the stage-1 field
+  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
+    return cf::launch_rk_stage<double>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g64, dt, nu, fx, s);
+  }));
+  // g* = g1 - W G L^+ D (g1 / W)
+  cx<double>* A = static_cast<cx<double>*>(pl->specA);
+  cx<double>* B = static_cast<cx<double>*>(pl->specB);
+  CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+weighted div launch", [&] {
+    return cf::launch_r2c_divw<double, double>(pl->nh, g1u, g1v, g1w, pl->d_rdy, pl->g64.rdyc, 1.0 / pl->dx,
+                                               1.0 / pl->dz, A, pl->tw_x64, pl->twp64, pl->ny, pl->nz, s);
+  }));
+  CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+    return cf::launch_fft_z<double>(pl->nz, false, A, B, pl->tw_z64, pl->ny, pl->nkx, s);
+  }));
+  CF_TRY(solve_t<double>(pl, B, B, s));
+  CF_TRY(inverse_t<double>(pl, B, pl->pws, s));
+  CF_TRY(timed(pl, CF_K_ADJ_CORRECT, s, "weighted correction", [&] {
+    return cf::launch_correct_w<double>(g1u, g1v, g1w, su, sv, sw, pl->pws, pl->a64, s);
+  }));
+  // gb = dt/2 J_R(ub)^T g*
+  CF_TRY(timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
+    return cf::launch_rhs_adjoint<double>(ub, vb, wb, su, sv, sw, nullptr, nullptr, nullptr, 1.0, 0.0, pl->a64, nu,
+                                          0.5 * dt, 0, bu, bv, bw, s);
+  }));
+  // g = g* + gb + J_R(u)^T (dt/2 g* + dt gb)
+  CF_TRY(timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
+    return cf::launch_rhs_adjoint<double>(u, v, w, su, sv, sw, bu, bv, bw, 0.5 * dt, dt, pl->a64, nu, 1.0, 1, gu, gv,
+                                          gw, s);
+  }));
+  return CF_OK;
+}
+
 // Elimination factors of one whole-line solve, in the operation order of the
 // textbook Thomas algorithm (no contraction).
 void special_factors(const cf_plan* pl, int line, double* den, double* cp) {
@@ -688,6 +740,13 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     pl->g64 = cf::Geo<double>{pl->d_rdy, pl->d_rdyc, pl->d_wl, pl->d_wu, rdx, rdz, rdx * rdx, rdz * rdz, nx, ny, nz};
     pl->g32 = cf::Geo<float>{pl->s_rdy, pl->s_rdyc, pl->s_wl, pl->s_wu, (float)rdx, (float)rdz,
                              (float)(rdx * rdx), (float)(rdz * rdz), nx, ny, nz};
+    std::vector<double> dyc(std::max(ny - 1, 1), 1.0);
+    for (int j = 0; j + 1 < ny; ++j) dyc[j] = pl->dyc[j];
+    if ((st = upload(pl, &pl->d_dyc, dyc)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_dy, tof(pl->dy))) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->s_dyc, tof(dyc))) != CF_OK) return bail(st);
+    pl->a64 = cf::AdjGeo<double>{pl->g64, pl->d_dy, pl->d_dyc, pl->d_rdyc};
+    pl->a32 = cf::AdjGeo<float>{pl->g32, pl->s_dy, pl->s_dyc, pl->s_rdyc};
   }
   if (opt.precision == CF_MIXED && opt.refine_passes > 0) {
     if ((st = dalloc(pl, &pl->fws, (size_t)nx * ny * nz)) != CF_OK) return bail(st);
@@ -712,6 +771,20 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
       pl->wb = c;
     }
     if ((st = dalloc(pl, &pl->pws, npts)) != CF_OK) return bail(st);
+    if (opt.flags & CF_PLAN_ADJOINT) {
+      void** slots[6] = {&pl->gsu, &pl->gsv, &pl->gsw, &pl->gbu, &pl->gbv, &pl->gbw};
+      for (void** sl : slots) {
+        if (opt.precision == CF_FP64) {
+          double* a = nullptr;
+          if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
+          *sl = a;
+        } else {
+          float* a = nullptr;
+          if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
+          *sl = a;
+        }
+      }
+    }
   }
   if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
   {
@@ -835,6 +908,53 @@ cf_status cf_projection_step(cf_plan* pl, const void* u, const void* v, const vo
                 static_cast<double*>(u1), static_cast<double*>(v1), static_cast<double*>(w1), p, dt, nu, fx, s);
 }
 
+cf_status cf_projection_step_adjoint(cf_plan* pl, const void* u, const void* v, const void* w,
+                                     const void* gu1, const void* gv1, const void* gw1, void* gu, void* gv,
+                                     void* gw, double dt, double nu, double fx, void* stream) {
+  CF_TRY(check_plan(pl));
+  if (!(pl->opt.flags & CF_PLAN_STEP) || !(pl->opt.flags & CF_PLAN_ADJOINT))
+    return fail(CF_ERR_ARG, "plan was created without CF_PLAN_STEP | CF_PLAN_ADJOINT");
+  const void* ptrs[9] = {u, v, w, gu1, gv1, gw1, gu, gv, gw};
+  const char* names[9] = {"u", "v", "w", "gu1", "gv1", "gw1", "gu", "gv", "gw"};
+  for (int q = 0; q < 9; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  for (int q = 6; q < 9; ++q)
+    for (int r = 0; r < 3; ++r)
+      if (ptrs[q] == ptrs[r]) return fail(CF_ERR_ARG, "the gradient output must not alias the step input");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
+  if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed()) return fail(CF_ERR_UNSUPPORTED, "mixed-precision adjoint is not built yet");
+  return step_adjoint64(pl, static_cast<const double*>(u), static_cast<const double*>(v),
+                        static_cast<const double*>(w), static_cast<const double*>(gu1), static_cast<const double*>(gv1),
+                        static_cast<const double*>(gw1), static_cast<double*>(gu), static_cast<double*>(gv),
+                        static_cast<double*>(gw), dt, nu, fx, s);
+}
+
+cf_status cf_rhs_adjoint(cf_plan* pl, const void* u, const void* v, const void* w, const void* lu, const void* lv,
+                         const void* lw, void* gu, void* gv, void* gw, double nu, void* stream) {
+  CF_TRY(check_plan(pl));
+  const void* ptrs[9] = {u, v, w, lu, lv, lw, gu, gv, gw};
+  const char* names[9] = {"u", "v", "w", "lu", "lv", "lw", "gu", "gv", "gw"};
+  for (int q = 0; q < 9; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(CF_ERR_ARG, "nu must be finite and >= 0");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed())
+    return timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
+      return cf::launch_rhs_adjoint<float>(
+          static_cast<const float*>(u), static_cast<const float*>(v), static_cast<const float*>(w),
+          static_cast<const float*>(lu), static_cast<const float*>(lv), static_cast<const float*>(lw), nullptr, nullptr,
+          nullptr, 1.0f, 0.0f, pl->a32, (float)nu, 1.0f, 0, static_cast<float*>(gu), static_cast<float*>(gv),
+          static_cast<float*>(gw), s);
+    });
+  return timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
+    return cf::launch_rhs_adjoint<double>(
+        static_cast<const double*>(u), static_cast<const double*>(v), static_cast<const double*>(w),
+        static_cast<const double*>(lu), static_cast<const double*>(lv), static_cast<const double*>(lw), nullptr,
+        nullptr, nullptr, 1.0, 0.0, pl->a64, nu, 1.0, 0, static_cast<double*>(gu), static_cast<double*>(gv),
+        static_cast<double*>(gw), s);
+  });
+}
+
 cf_status cf_plan_set_timing(cf_plan* pl, int enable) {
   CF_TRY(check_plan(pl));
   if (!enable) CF_TRY(harvest(pl));
@@ -863,8 +983,9 @@ cf_status cf_plan_get_timing(cf_plan* pl, int kernel, double* total_ms, long lon
 }
 
 const char* cf_kernel_name(int k) {
-  static const char* names[CF_K_COUNT] = {"r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv",
-                                          "c2r_x", "divergence", "rk_stage1", "rk_stage2", "correct"};
+  static const char* names[CF_K_COUNT] = {"r2c_x",     "fft_z_fwd", "ysolve",      "special_lines",
+                                          "fft_z_inv", "c2r_x",     "divergence",  "rk_stage1",
+                                          "rk_stage2", "correct",   "rhs_adjoint", "correct_weighted"};
   return (k >= 0 && k < CF_K_COUNT) ? names[k] : "unknown";
 }
 

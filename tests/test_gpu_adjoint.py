@@ -1,0 +1,115 @@
+"""Hand-written adjoint of the projection step against autograd of the FP64
+oracle, finite differences, and checkpointed vs stored rollouts."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def setup(nx, ny, nz, gamma, lx=2 * np.pi, lz=np.pi):
+    from paper_2104_08863_amd.api import Plan
+    yf = synth.tanh_faces(ny, gamma)
+    return Plan(nx, ny, nz, lx, lz, yf, adjoint=True), O.Box(nx, ny, nz, lx, lz, yf)
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma", [(16, 12, 8, 2.0), (32, 16, 24, 2.5), (12, 8, 6, 1.0)])
+def test_rhs_adjoint_matches_autograd(nx, ny, nz, gamma):
+    pl, box = setup(nx, ny, nz, gamma)
+    nu = 1 / 100
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=1)
+    lam = synth.random_directions(nx, ny, nz, seed=7)
+    ut = [torch.tensor(q, requires_grad=True) for q in (u, v, w)]
+    r = O.momentum_rhs(*ut, box, nu, 0.3)
+    ref = torch.autograd.grad(r, ut, grad_outputs=[torch.tensor(q) for q in lam])
+    got = pl.rhs_adjoint(*(torch.tensor(q, device=dev()) for q in (u, v, w)),
+                         *(torch.tensor(q, device=dev()) for q in lam), nu)
+    for g, want, name in zip(got, ref, "uvw"):
+        e = rel(g.cpu().numpy(), want.numpy())
+        assert e <= 1e-12, f"{name}: {e:.3e}"
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,dt,nu", [(32, 16, 24, 2.0, 1e-3, 1 / 550),
+                                                   (24, 12, 12, 2.5, 5e-3, 1 / 50),
+                                                   (64, 32, 48, 2.0, 1e-3, 1 / 550)])
+def test_step_adjoint_matches_oracle_gradient(nx, ny, nz, gamma, dt, nu):
+    pl, box = setup(nx, ny, nz, gamma)
+    fx = 3 * nu
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=2)
+    g1 = synth.random_directions(nx, ny, nz, seed=3)
+    ut = [torch.tensor(q, requires_grad=True) for q in (u, v, w)]
+    out = O.projection_step(*ut, box, dt, nu, fx)
+    ref = torch.autograd.grad(out, ut, grad_outputs=[torch.tensor(q) for q in g1])
+    got = pl.projection_step_adjoint(*(torch.tensor(q, device=dev()) for q in (u, v, w)),
+                                     *(torch.tensor(q, device=dev()) for q in g1), dt, nu, fx)
+    for g, want, name in zip(got, ref, "uvw"):
+        e = rel(g.cpu().numpy(), want.numpy())
+        assert e <= 1e-10, f"{name}: {e:.3e}"
+    assert bool(torch.all(got[1][-1] == 0))
+
+
+def test_rollout_gradient_matches_oracle_and_checkpointing_is_exact():
+    from paper_2104_08863_amd import autograd as AG
+    nx, ny, nz = 32, 16, 24
+    pl, box = setup(nx, ny, nz, 2.0)
+    dt, nu, fx = 2e-3, 1 / 200, 3 / 200
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=4)
+    _, gu_o, gv_o, gw_o = O.rollout_loss_and_grad(*(torch.tensor(q) for q in (u, v, w)), box, 4, dt, nu, fx)
+    grads = []
+    for every in (1, 2, 4):
+        xs = [torch.tensor(q, device=dev(), requires_grad=True) for q in (u, v, w)]
+        a, b, c = AG.rollout(pl, *xs, 4, dt, nu, fx, checkpoint_every=every)
+        loss = 0.5 * ((a * a).sum() + (b * b).sum() + (c * c).sum())
+        loss.backward()
+        grads.append([x.grad.detach().clone() for x in xs])
+    for g in grads[1:]:
+        for x, y in zip(g, grads[0]):
+            assert torch.equal(x, y)
+    for g, want in zip(grads[0], (gu_o, gv_o, gw_o)):
+        assert rel(g.cpu().numpy(), want.numpy()) <= 1e-10
+
+
+def test_rollout_finite_differences_256x128x256():
+    """The differentiable-rollout workload: 8 FP64 steps on 256x128x256, dt 1e-3,
+    nu 1/550, checkpoints every 2 steps, loss 0.5 sum(u^2 + v^2 + w^2); the
+    adjoint gradient's projection on 16 random directions matches central
+    differences (h = 1e-4) to 1e-6."""
+    from paper_2104_08863_amd import autograd as AG
+    wl = synth.WORKLOADS["rollout256"]
+    pl, box = setup(wl.nx, wl.ny, wl.nz, wl.gamma, wl.lx, wl.lz)
+    u, v, w = (torch.tensor(q, device=dev()) for q in
+               synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, box.y_faces, seed=0))
+    xs = [t.clone().requires_grad_(True) for t in (u, v, w)]
+    a, b, c = AG.rollout(pl, *xs, 8, wl.dt, wl.nu, wl.fx, checkpoint_every=2)
+    (0.5 * ((a * a).sum() + (b * b).sum() + (c * c).sum())).backward()
+    g = [x.grad for x in xs]
+
+    def J(p, q, r):
+        with torch.no_grad():
+            s = (p, q, r)
+            for _ in range(8):
+                s = pl.projection_step(*s, wl.dt, wl.nu, wl.fx)
+            return 0.5 * sum(float((t * t).sum()) for t in s)
+
+    worst = 0.0
+    for seed in range(1, 17):
+        d = [torch.tensor(q, device=dev()) for q in synth.random_directions(wl.nx, wl.ny, wl.nz, seed)]
+        h = 1e-4
+        fd = (J(*(x + h * e for x, e in zip((u, v, w), d))) - J(*(x - h * e for x, e in zip((u, v, w), d)))) / (2 * h)
+        an = sum(float((gi * e).sum()) for gi, e in zip(g, d))
+        err = abs(fd - an) / max(abs(fd), abs(an))
+        worst = max(worst, err)
+        assert err <= 1e-6, f"direction {seed}: FD {fd:.12e} adjoint {an:.12e} rel {err:.2e}"
+    print(f"rollout FD check: worst relative error over 16 directions {worst:.2e}")
