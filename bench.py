@@ -25,6 +25,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch; FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors
+# a plain elementwise kernel reading and writing a known size gives on this
+# chip).  Keyed by (kernel, workload); drop an entry when its kernel changes.
+MEASURED_TRAFFIC = {
+    ("rk_stage2", "step550"): (4189164.2 * 2.0 + 3145728.0 * 1.0) * 1024,
+}
+
 
 def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_phys: int = 8,
                  fused_div: bool = False) -> float:
@@ -85,6 +93,78 @@ def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
                       f"ny reduced from {wl.ny}), mean of {n} calls"}
 
 
+def _time(fn, steps, warmup=2):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def secondary(wl, steps):
+    """The other figures of the headline metric, each timed on resident inputs:
+    FP64 vs mixed (FP32 + one FP64 refinement) Poisson solves on the step grid
+    and on the 2048x512x1536 grid, and the FP64 forward + adjoint step."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    res = {}
+    npts = wl.nx * wl.ny * wl.nz
+    yf = wl.y_faces()
+    f = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0), device=dev)
+    p64 = torch.empty_like(f)
+    pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64")
+    t = _time(lambda: pl.poisson_solve(f, out=p64), steps)
+    res["poisson_fp64"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
+                           "Mpts_s": round(npts / t / 1e6, 1), "model_GBps": round(80 * npts / t / 1e9, 1)}
+    del pl
+    pm = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="mixed", refine_passes=1)
+    pmx = torch.empty_like(f)
+    t = _time(lambda: pm.poisson_solve(f, out=pmx), steps)
+    err = float(torch.linalg.vector_norm(pmx - p64) / torch.linalg.vector_norm(p64))
+    res["poisson_mixed_refine1"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
+                                    "Mpts_s": round(npts / t / 1e6, 1),
+                                    "rel_l2_vs_fp64_gpu": err}
+    del pm, pmx, p64, f
+    torch.cuda.empty_cache()
+    # forward + adjoint step, FP64
+    pa = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64", adjoint=True)
+    u, v, w = (torch.tensor(q, device=dev) for q in synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0))
+    o = tuple(torch.empty_like(u) for _ in range(3))
+    g1 = tuple(torch.tensor(q, device=dev) for q in synth.random_directions(wl.nx, wl.ny, wl.nz, seed=1))
+    go = tuple(torch.empty_like(u) for _ in range(3))
+
+    def fwd_adj():
+        pa.projection_step(u, v, w, wl.dt, wl.nu, wl.fx, out=o)
+        pa.projection_step_adjoint(u, v, w, *g1, wl.dt, wl.nu, wl.fx, out=go)
+    t = _time(fwd_adj, steps)
+    res["fwd_adjoint_step_fp64"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
+                                    "Mpts_s": round(npts / t / 1e6, 1)}
+    del pa, u, v, w, o, g1, go
+    torch.cuda.empty_cache()
+    # mixed-precision Poisson solve on the Re_tau=1000-shaped grid
+    big = synth.WORKLOADS["mixed1000"]
+    nb = big.nx * big.ny * big.nz
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    fb = torch.rand(big.ny, big.nz, big.nx, dtype=torch.float64, device=dev, generator=gen) * 2 - 1
+    pb = torch.empty_like(fb)
+    pm = Plan(big.nx, big.ny, big.nz, big.lx, big.lz, big.y_faces(), precision="mixed", refine_passes=1)
+    t = _time(lambda: pm.poisson_solve(fb, out=pb), max(2, steps // 2), warmup=1)
+    res["poisson_mixed_refine1_2048x512x1536"] = {
+        "grid": [big.nx, big.ny, big.nz], "ms": round(t * 1e3, 3), "Mpts_s": round(nb / t / 1e6, 1),
+        "input": "uniform[-1,1] RHS from a seeded torch CUDA generator"}
+    del pm, pb, fb
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,9 +172,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="step550")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--secondary-steps", type=int, default=6,
+                    help="timed calls per secondary figure (Poisson FP64/mixed, fwd+adjoint)")
     ap.add_argument("--poisson-only", action="store_true",
                     help="time the Poisson solve alone instead of the projection step")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain elementwise kernel reading and writing BYTES bytes "
+                         "three times (reference for hardware traffic counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.add(a, 1.0, out=b)   # one kernel: reads n*8 bytes, writes n*8 bytes
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU split is a design note, not built", file=sys.stderr)
@@ -155,6 +250,7 @@ def main():
                   for k, v in kern.items()}
     model_bytes = sum(kb(k) * v[1] for k, v in kern.items()) / args.steps
     what = "FP64 pressure-Poisson solve" if args.poisson_only else "FP64 projection step (RK2 + Poisson + correction)"
+    traffic = MEASURED_TRAFFIC.get((dom, wl.name)) if not args.poisson_only else None
     out = {
         "metric": ("Mpts/s per FP64 Poisson solve (FFT x,z + PDD y), % HBM" if args.poisson_only
                    else "Mpts/s per FP64 projection step (RK2 + FFT/PDD Poisson + correction), % HBM"),
@@ -177,10 +273,14 @@ def main():
                    "lines": info["n_lines"]},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": traffic, "algorithmic_bytes": nbytes},
         "model_GBps_whole_step": round(model_bytes / (ms * 1e-3) / 1e9, 1),
         "kernels": per_kernel,
     }
+    if not args.poisson_only:
+        del u, v, w, outs, p, plan
+        torch.cuda.empty_cache()
+        out["also"] = secondary(wl, args.secondary_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.poisson_only)
     print(json.dumps(out), flush=True)

@@ -34,165 +34,240 @@ struct AdjGeo {
   const T* rdyc;  // 1/dyc
 };
 
-// Global-memory accessor with periodic x, z and the wall rules; lam is formed
-// as c1 * A + c2 * B on the fly.
+// J_R(u)^T lam at point (i, j, k) from an accessor with relative offsets:
+// A.U(dj, dk, di) etc. for the state and A.LU(...) for lam; A returns 0 outside
+// [0, ny) and for v / lam_v on the top wall.
 template <typename T>
-struct AdjAcc {
-  const T *u, *v, *w;
-  const T *au, *av, *aw, *bu, *bv, *bw;
-  T c1, c2;
-  int nx, ny, nz;
-  __device__ __forceinline__ long at(int j, int k, int i) const {
-    k = (k < 0) ? k + nz : (k >= nz ? k - nz : k);
-    i = (i < 0) ? i + nx : (i >= nx ? i - nx : i);
-    return ((long)j * nz + k) * nx + i;
-  }
-  __device__ __forceinline__ bool yin(int j) const { return j >= 0 && j < ny; }
-  __device__ __forceinline__ bool vin(int j) const { return j >= 0 && j < ny - 1; }
-  __device__ __forceinline__ T U(int j, int k, int i) const { return yin(j) ? u[at(j, k, i)] : T(0); }
-  __device__ __forceinline__ T V(int j, int k, int i) const { return vin(j) ? v[at(j, k, i)] : T(0); }
-  __device__ __forceinline__ T W(int j, int k, int i) const { return yin(j) ? w[at(j, k, i)] : T(0); }
-  __device__ __forceinline__ T lam(const T* a, const T* b, long o) const {
-    return b ? c1 * a[o] + c2 * b[o] : c1 * a[o];
-  }
-  __device__ __forceinline__ T LU(int j, int k, int i) const { return yin(j) ? lam(au, bu, at(j, k, i)) : T(0); }
-  __device__ __forceinline__ T LV(int j, int k, int i) const { return vin(j) ? lam(av, bv, at(j, k, i)) : T(0); }
-  __device__ __forceinline__ T LW(int j, int k, int i) const { return yin(j) ? lam(aw, bw, at(j, k, i)) : T(0); }
+struct AdjOut {
+  T gu, gv, gw;
 };
 
-// out = s * J_R(u)^T lam (+ A + B when add), lam = c1 A + c2 B.
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_rhs_adjoint(AdjAcc<T> X, AdjGeo<T> G, T nu, T s, int add, T* __restrict__ gu, T* __restrict__ gv,
-              T* __restrict__ gw) {
+template <typename T, class Acc>
+__device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGeo<T>& G, int j, T nu) {
   const Geo<T>& g = G.g;
-  const long n = (long)g.nx * g.ny * g.nz;
-  const long id = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n) return;
-  const int i = int(id % g.nx);
-  const long jk = id / g.nx;
-  const int k = int(jk % g.nz);
-  const int j = int(jk / g.nz);
   const int ny = g.ny;
   const T h = T(0.5);
   const T rdx = g.rdx, rdz = g.rdz;
   const bool top = (j == ny - 1), bot = (j == 0);
-  auto rdyv = [&](int jj) { return (jj >= 0 && jj < ny) ? g.rdy[jj] : T(0); };
-
+  const T ry0 = g.rdy[j];
+  const T ryp = top ? T(0) : g.rdy[j + 1];
+  const T rym = bot ? T(0) : g.rdy[j - 1];
+  AdjOut<T> o;
   // ---------------- u point (i+1/2, j, k)
-  T nu_u;
   {
-    // (1) centre squares along x
-    const T uc0 = h * (X.U(j, k, i) + X.U(j, k, i - 1));
-    const T uc1 = h * (X.U(j, k, i + 1) + X.U(j, k, i));
-    const T xi0 = (X.LU(j, k, i - 1) - X.LU(j, k, i)) * rdx;
-    const T xi1 = (X.LU(j, k, i) - X.LU(j, k, i + 1)) * rdx;
+    const T uc0 = h * (A.U(0, 0, 0) + A.U(0, 0, -1));
+    const T uc1 = h * (A.U(0, 0, 1) + A.U(0, 0, 0));
+    const T xi0 = (A.LU(0, 0, -1) - A.LU(0, 0, 0)) * rdx;
+    const T xi1 = (A.LU(0, 0, 0) - A.LU(0, 0, 1)) * rdx;
     T acc = uc0 * xi0 + uc1 * xi1;
-    // (2) x-y edges at faces j+1 (weight wl_j) and j (weight wu_{j-1})
     if (!top) {
-      const T mu = X.LU(j, k, i) * g.rdy[j] - X.LU(j + 1, k, i) * g.rdy[j + 1] +
-                   (X.LV(j, k, i) - X.LV(j, k, i + 1)) * rdx;
-      acc += mu * (h * (X.V(j, k, i) + X.V(j, k, i + 1))) * g.wl[j];
+      const T mu = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
+      acc += mu * (h * (A.V(0, 0, 0) + A.V(0, 0, 1))) * g.wl[j];
     }
     if (!bot) {
-      const T mu = X.LU(j - 1, k, i) * g.rdy[j - 1] - X.LU(j, k, i) * g.rdy[j] +
-                   (X.LV(j - 1, k, i) - X.LV(j - 1, k, i + 1)) * rdx;
-      acc += mu * (h * (X.V(j - 1, k, i) + X.V(j - 1, k, i + 1))) * g.wu[j - 1];
+      const T mu = A.LU(-1, 0, 0) * rym - A.LU(0, 0, 0) * ry0 + (A.LV(-1, 0, 0) - A.LV(-1, 0, 1)) * rdx;
+      acc += mu * (h * (A.V(-1, 0, 0) + A.V(-1, 0, 1))) * g.wu[j - 1];
     }
-    // (3) x-z edges at k+1/2 and k-1/2
     {
-      const T mk0 = (X.LU(j, k, i) - X.LU(j, k + 1, i)) * rdz + (X.LW(j, k, i) - X.LW(j, k, i + 1)) * rdx;
-      const T mk1 = (X.LU(j, k - 1, i) - X.LU(j, k, i)) * rdz + (X.LW(j, k - 1, i) - X.LW(j, k - 1, i + 1)) * rdx;
-      acc += h * (mk0 * (h * (X.W(j, k, i) + X.W(j, k, i + 1))) + mk1 * (h * (X.W(j, k - 1, i) + X.W(j, k - 1, i + 1))));
+      const T mk0 = (A.LU(0, 0, 0) - A.LU(0, 1, 0)) * rdz + (A.LW(0, 0, 0) - A.LW(0, 0, 1)) * rdx;
+      const T mk1 = (A.LU(0, -1, 0) - A.LU(0, 0, 0)) * rdz + (A.LW(0, -1, 0) - A.LW(0, -1, 1)) * rdx;
+      acc += h * (mk0 * (h * (A.W(0, 0, 0) + A.W(0, 0, 1))) + mk1 * (h * (A.W(0, -1, 0) + A.W(0, -1, 1))));
     }
-    // Laplacian transpose
-    const T l0 = X.LU(j, k, i);
-    T lap = (X.LU(j, k, i + 1) - T(2) * l0 + X.LU(j, k, i - 1)) * g.rdx2 +
-            (X.LU(j, k + 1, i) - T(2) * l0 + X.LU(j, k - 1, i)) * g.rdz2;
-    const T q0 = l0 * g.rdy[j];
-    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (X.LU(j + 1, k, i) * rdyv(j + 1) - q0) * g.rdyc[j];
-    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - X.LU(j - 1, k, i) * rdyv(j - 1)) * g.rdyc[j - 1];
+    const T l0 = A.LU(0, 0, 0);
+    T lap = (A.LU(0, 0, 1) - T(2) * l0 + A.LU(0, 0, -1)) * g.rdx2 + (A.LU(0, 1, 0) - T(2) * l0 + A.LU(0, -1, 0)) * g.rdz2;
+    const T q0 = l0 * ry0;
+    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (A.LU(1, 0, 0) * ryp - q0) * g.rdyc[j];
+    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - A.LU(-1, 0, 0) * rym) * g.rdyc[j - 1];
     lap += ft - fb;
-    nu_u = -acc + nu * lap;
+    o.gu = -acc + nu * lap;
   }
   // ---------------- w point (i, j, k+1/2)
-  T nu_w;
   {
-    // (6) centre squares along z
-    const T wc0 = h * (X.W(j, k, i) + X.W(j, k - 1, i));
-    const T wc1 = h * (X.W(j, k + 1, i) + X.W(j, k, i));
-    const T xi0 = (X.LW(j, k - 1, i) - X.LW(j, k, i)) * rdz;
-    const T xi1 = (X.LW(j, k, i) - X.LW(j, k + 1, i)) * rdz;
+    const T wc0 = h * (A.W(0, 0, 0) + A.W(0, -1, 0));
+    const T wc1 = h * (A.W(0, 1, 0) + A.W(0, 0, 0));
+    const T xi0 = (A.LW(0, -1, 0) - A.LW(0, 0, 0)) * rdz;
+    const T xi1 = (A.LW(0, 0, 0) - A.LW(0, 1, 0)) * rdz;
     T acc = wc0 * xi0 + wc1 * xi1;
-    // (3) x-z edges at i+1/2 and i-1/2
     {
-      const T m0 = (X.LU(j, k, i) - X.LU(j, k + 1, i)) * rdz + (X.LW(j, k, i) - X.LW(j, k, i + 1)) * rdx;
-      const T m1 = (X.LU(j, k, i - 1) - X.LU(j, k + 1, i - 1)) * rdz + (X.LW(j, k, i - 1) - X.LW(j, k, i)) * rdx;
-      acc += h * (m0 * (h * (X.U(j, k, i) + X.U(j, k + 1, i))) + m1 * (h * (X.U(j, k, i - 1) + X.U(j, k + 1, i - 1))));
+      const T m0 = (A.LU(0, 0, 0) - A.LU(0, 1, 0)) * rdz + (A.LW(0, 0, 0) - A.LW(0, 0, 1)) * rdx;
+      const T m1 = (A.LU(0, 0, -1) - A.LU(0, 1, -1)) * rdz + (A.LW(0, 0, -1) - A.LW(0, 0, 0)) * rdx;
+      acc += h * (m0 * (h * (A.U(0, 0, 0) + A.U(0, 1, 0))) + m1 * (h * (A.U(0, 0, -1) + A.U(0, 1, -1))));
     }
-    // (4) y-z edges at faces j+1 and j
     if (!top) {
-      const T mu = (X.LV(j, k, i) - X.LV(j, k + 1, i)) * rdz + X.LW(j, k, i) * g.rdy[j] -
-                   X.LW(j + 1, k, i) * g.rdy[j + 1];
-      acc += mu * (h * (X.V(j, k, i) + X.V(j, k + 1, i))) * g.wl[j];
+      const T mu = (A.LV(0, 0, 0) - A.LV(0, 1, 0)) * rdz + A.LW(0, 0, 0) * ry0 - A.LW(1, 0, 0) * ryp;
+      acc += mu * (h * (A.V(0, 0, 0) + A.V(0, 1, 0))) * g.wl[j];
     }
     if (!bot) {
-      const T mu = (X.LV(j - 1, k, i) - X.LV(j - 1, k + 1, i)) * rdz + X.LW(j - 1, k, i) * g.rdy[j - 1] -
-                   X.LW(j, k, i) * g.rdy[j];
-      acc += mu * (h * (X.V(j - 1, k, i) + X.V(j - 1, k + 1, i))) * g.wu[j - 1];
+      const T mu = (A.LV(-1, 0, 0) - A.LV(-1, 1, 0)) * rdz + A.LW(-1, 0, 0) * rym - A.LW(0, 0, 0) * ry0;
+      acc += mu * (h * (A.V(-1, 0, 0) + A.V(-1, 1, 0))) * g.wu[j - 1];
     }
-    const T l0 = X.LW(j, k, i);
-    T lap = (X.LW(j, k, i + 1) - T(2) * l0 + X.LW(j, k, i - 1)) * g.rdx2 +
-            (X.LW(j, k + 1, i) - T(2) * l0 + X.LW(j, k - 1, i)) * g.rdz2;
-    const T q0 = l0 * g.rdy[j];
-    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (X.LW(j + 1, k, i) * rdyv(j + 1) - q0) * g.rdyc[j];
-    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - X.LW(j - 1, k, i) * rdyv(j - 1)) * g.rdyc[j - 1];
+    const T l0 = A.LW(0, 0, 0);
+    T lap = (A.LW(0, 0, 1) - T(2) * l0 + A.LW(0, 0, -1)) * g.rdx2 + (A.LW(0, 1, 0) - T(2) * l0 + A.LW(0, -1, 0)) * g.rdz2;
+    const T q0 = l0 * ry0;
+    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (A.LW(1, 0, 0) * ryp - q0) * g.rdyc[j];
+    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - A.LW(-1, 0, 0) * rym) * g.rdyc[j - 1];
     lap += ft - fb;
-    nu_w = -acc + nu * lap;
+    o.gw = -acc + nu * lap;
   }
   // ---------------- v point (i, face j+1, k), interior faces only
-  T nu_v = T(0);
+  o.gv = T(0);
   if (!top) {
-    // (5) centre squares along y: centres j and j+1
-    const T vc0 = h * (X.V(j, k, i) + X.V(j - 1, k, i));
-    const T vc1 = h * (X.V(j + 1, k, i) + X.V(j, k, i));
-    const T xi0 = (bot ? T(0) : X.LV(j - 1, k, i) * G.rdyc[j - 1]) - X.LV(j, k, i) * G.rdyc[j];
-    const T xi1 = X.LV(j, k, i) * G.rdyc[j] - ((j + 1 < ny - 1) ? X.LV(j + 1, k, i) * G.rdyc[j + 1] : T(0));
+    const T rc0 = G.rdyc[j];
+    const T rcm = bot ? T(0) : G.rdyc[j - 1];
+    const T rcp = (j + 1 < ny - 1) ? G.rdyc[j + 1] : T(0);
+    const T vc0 = h * (A.V(0, 0, 0) + A.V(-1, 0, 0));
+    const T vc1 = h * (A.V(1, 0, 0) + A.V(0, 0, 0));
+    const T xi0 = A.LV(-1, 0, 0) * rcm - A.LV(0, 0, 0) * rc0;
+    const T xi1 = A.LV(0, 0, 0) * rc0 - A.LV(1, 0, 0) * rcp;
     T acc = vc0 * xi0 + vc1 * xi1;
-    // (2) x-y edges at i+1/2 and i-1/2 (face j+1)
+    const T a = g.wl[j], b = g.wu[j];
     {
-      const T a = g.wl[j], b = g.wu[j];
-      const T m0 = X.LU(j, k, i) * g.rdy[j] - X.LU(j + 1, k, i) * g.rdy[j + 1] + (X.LV(j, k, i) - X.LV(j, k, i + 1)) * rdx;
-      const T m1 = X.LU(j, k, i - 1) * g.rdy[j] - X.LU(j + 1, k, i - 1) * g.rdy[j + 1] +
-                   (X.LV(j, k, i - 1) - X.LV(j, k, i)) * rdx;
-      acc += h * (m0 * (X.U(j, k, i) * a + X.U(j + 1, k, i) * b) + m1 * (X.U(j, k, i - 1) * a + X.U(j + 1, k, i - 1) * b));
+      const T m0 = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
+      const T m1 = A.LU(0, 0, -1) * ry0 - A.LU(1, 0, -1) * ryp + (A.LV(0, 0, -1) - A.LV(0, 0, 0)) * rdx;
+      acc += h * (m0 * (A.U(0, 0, 0) * a + A.U(1, 0, 0) * b) + m1 * (A.U(0, 0, -1) * a + A.U(1, 0, -1) * b));
     }
-    // (4) y-z edges at k+1/2 and k-1/2 (face j+1)
     {
-      const T a = g.wl[j], b = g.wu[j];
-      const T m0 = (X.LV(j, k, i) - X.LV(j, k + 1, i)) * rdz + X.LW(j, k, i) * g.rdy[j] - X.LW(j + 1, k, i) * g.rdy[j + 1];
-      const T m1 = (X.LV(j, k - 1, i) - X.LV(j, k, i)) * rdz + X.LW(j, k - 1, i) * g.rdy[j] -
-                   X.LW(j + 1, k - 1, i) * g.rdy[j + 1];
-      acc += h * (m0 * (X.W(j, k, i) * a + X.W(j + 1, k, i) * b) + m1 * (X.W(j, k - 1, i) * a + X.W(j + 1, k - 1, i) * b));
+      const T m0 = (A.LV(0, 0, 0) - A.LV(0, 1, 0)) * rdz + A.LW(0, 0, 0) * ry0 - A.LW(1, 0, 0) * ryp;
+      const T m1 = (A.LV(0, -1, 0) - A.LV(0, 0, 0)) * rdz + A.LW(0, -1, 0) * ry0 - A.LW(1, -1, 0) * ryp;
+      acc += h * (m0 * (A.W(0, 0, 0) * a + A.W(1, 0, 0) * b) + m1 * (A.W(0, -1, 0) * a + A.W(1, -1, 0) * b));
     }
-    const T l0 = X.LV(j, k, i);
-    T lap = (X.LV(j, k, i + 1) - T(2) * l0 + X.LV(j, k, i - 1)) * g.rdx2 +
-            (X.LV(j, k + 1, i) - T(2) * l0 + X.LV(j, k - 1, i)) * g.rdz2;
-    const T q0 = l0 * G.rdyc[j];
-    const T qp = (j + 1 < ny - 1) ? X.LV(j + 1, k, i) * G.rdyc[j + 1] : T(0);
-    const T qm = bot ? T(0) : X.LV(j - 1, k, i) * G.rdyc[j - 1];
-    lap += (qp - q0) * g.rdy[j + 1] - (q0 - qm) * g.rdy[j];
-    nu_v = -acc + nu * lap;
+    const T l0 = A.LV(0, 0, 0);
+    T lap = (A.LV(0, 0, 1) - T(2) * l0 + A.LV(0, 0, -1)) * g.rdx2 + (A.LV(0, 1, 0) - T(2) * l0 + A.LV(0, -1, 0)) * g.rdz2;
+    const T q0 = l0 * rc0;
+    const T qp = A.LV(1, 0, 0) * rcp;
+    const T qm = A.LV(-1, 0, 0) * rcm;
+    lap += (qp - q0) * ryp - (q0 - qm) * ry0;
+    o.gv = -acc + nu * lap;
   }
-  T ou = s * nu_u, ov = s * nu_v, ow = s * nu_w;
-  if (add) {
-    ou += X.au[id] + (X.bu ? X.bu[id] : T(0));
-    ow += X.aw[id] + (X.bw ? X.bw[id] : T(0));
-    ov += top ? T(0) : X.av[id] + (X.bv ? X.bv[id] : T(0));
+  return o;
+}
+
+// LDS accessor: six fields (u, v, w, lam_u, lam_v, lam_w), three plane slots each.
+template <typename T, int TX, int TZ>
+struct AdjLdsAcc {
+  const T* s;      // 6 fields x 3 slots x PLANE
+  int sm, s0, sp;  // slot offsets (in elements) of planes j-1, j, j+1 within a field
+  int base;
+  static constexpr int SX = TX + 2, PLANE = (TX + 2) * (TZ + 2);
+  __device__ __forceinline__ int off(int f, int dj, int dk, int di) const {
+    return f * 3 * PLANE + (dj < 0 ? sm : (dj > 0 ? sp : s0)) + base + dk * SX + di;
   }
-  gu[id] = ou;
-  gv[id] = top ? T(0) : ov;
-  gw[id] = ow;
+  __device__ __forceinline__ T U(int dj, int dk, int di) const { return s[off(0, dj, dk, di)]; }
+  __device__ __forceinline__ T V(int dj, int dk, int di) const { return s[off(1, dj, dk, di)]; }
+  __device__ __forceinline__ T W(int dj, int dk, int di) const { return s[off(2, dj, dk, di)]; }
+  __device__ __forceinline__ T LU(int dj, int dk, int di) const { return s[off(3, dj, dk, di)]; }
+  __device__ __forceinline__ T LV(int dj, int dk, int di) const { return s[off(4, dj, dk, di)]; }
+  __device__ __forceinline__ T LW(int dj, int dk, int di) const { return s[off(5, dj, dk, di)]; }
+};
+
+struct AdjPtrs {
+  const void *u, *v, *w, *au, *av, *aw, *bu, *bv, *bw;
+  void *gu, *gv, *gw;
+};
+
+// out = s * J_R(state)^T lam (+ A + B when add), lam = c1 A + c2 B (B may be
+// null).  2.5D tiling as in k_rk_stage: a TX x TZ column tile marches over CY
+// planes keeping three planes of the six fields in LDS, the next plane fetched
+// into registers while the current one is computed.
+template <typename T, int TX, int TZ, int CY>
+__global__ void __launch_bounds__(TX * TZ)
+k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
+  constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, TH = TX * TZ;
+  constexpr int PER = (PLANE + TH - 1) / TH;
+  __shared__ T sm[6 * 3 * PLANE];
+  const T* u = static_cast<const T*>(P.u);
+  const T* v = static_cast<const T*>(P.v);
+  const T* w = static_cast<const T*>(P.w);
+  const T* au = static_cast<const T*>(P.au);
+  const T* av = static_cast<const T*>(P.av);
+  const T* aw = static_cast<const T*>(P.aw);
+  const T* bu = static_cast<const T*>(P.bu);
+  const T* bv = static_cast<const T*>(P.bv);
+  const T* bw = static_cast<const T*>(P.bw);
+  const bool hasb = (bu != nullptr);
+  const Geo<T>& g = G.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
+  const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
+  int b = blockIdx.x;
+  const int bx = b % ntx;
+  b /= ntx;
+  const int bz = b % ntz;
+  const int by = b / ntz;
+  const int i0 = bx * TX, k0 = bz * TZ;
+  const int j0 = by * CY, j1 = (j0 + CY < ny) ? j0 + CY : ny;
+  const int tx = threadIdx.x % TX, tz = threadIdx.x / TX;
+  const int i = i0 + tx, k = k0 + tz;
+  const bool mine = (i < nx) && (k < nz);
+  const long plane = (long)nx * nz;
+  int toff[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = threadIdx.x + q * TH;
+    const int zz = idx / SX, xx = idx % SX;
+    int gi = (i0 + xx - 1) % nx;
+    if (gi < 0) gi += nx;
+    int gk = (k0 + zz - 1) % nz;
+    if (gk < 0) gk += nz;
+    toff[q] = (idx < PLANE) ? gk * nx + gi : -1;
+  }
+  T r[6][PER];
+#define CF_ADJ_FETCH(jj)                                                        \
+  _Pragma("unroll") for (int q = 0; q < PER; ++q) {                            \
+    _Pragma("unroll") for (int f = 0; f < 6; ++f) r[f][q] = T(0);              \
+    if (toff[q] >= 0 && (jj) >= 0 && (jj) < ny) {                              \
+      const long o = (long)(jj) * plane + toff[q];                             \
+      r[0][q] = u[o];                                                          \
+      r[2][q] = w[o];                                                          \
+      r[3][q] = hasb ? c1 * au[o] + c2 * bu[o] : c1 * au[o];                    \
+      r[5][q] = hasb ? c1 * aw[o] + c2 * bw[o] : c1 * aw[o];                    \
+      if ((jj) < ny - 1) {                                                     \
+        r[1][q] = v[o];                                                        \
+        r[4][q] = hasb ? c1 * av[o] + c2 * bv[o] : c1 * av[o];                  \
+      }                                                                        \
+    }                                                                          \
+  }
+#define CF_ADJ_STORE(slot)                                                      \
+  _Pragma("unroll") for (int q = 0; q < PER; ++q) {                            \
+    if (toff[q] >= 0) {                                                        \
+      const int idx = threadIdx.x + q * TH;                                    \
+      _Pragma("unroll") for (int f = 0; f < 6; ++f) sm[(f * 3 + (slot)) * PLANE + idx] = r[f][q]; \
+    }                                                                          \
+  }
+  CF_ADJ_FETCH(j0 - 1)
+  CF_ADJ_STORE((j0 + 2) % 3)
+  CF_ADJ_FETCH(j0)
+  CF_ADJ_STORE(j0 % 3)
+  CF_ADJ_FETCH(j0 + 1)
+  AdjLdsAcc<T, TX, TZ> A{sm, 0, 0, 0, (tz + 1) * SX + tx + 1};
+  const long pid = (long)k * nx + i;
+  T* gu = static_cast<T*>(P.gu);
+  T* gv = static_cast<T*>(P.gv);
+  T* gw = static_cast<T*>(P.gw);
+  for (int j = j0; j < j1; ++j) {
+    CF_ADJ_STORE((j + 1) % 3)
+    __syncthreads();
+    CF_ADJ_FETCH(j + 2)
+    A.sm = ((j + 2) % 3) * PLANE;
+    A.s0 = (j % 3) * PLANE;
+    A.sp = ((j + 1) % 3) * PLANE;
+    if (mine) {
+      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, j, nu);
+      const long id = (long)j * plane + pid;
+      const bool top = (j == ny - 1);
+      T ou = s * o.gu, ov = s * o.gv, ow = s * o.gw;
+      if (add) {
+        ou += au[id] + (hasb ? bu[id] : T(0));
+        ow += aw[id] + (hasb ? bw[id] : T(0));
+        ov += top ? T(0) : av[id] + (hasb ? bv[id] : T(0));
+      }
+      gu[id] = ou;
+      gv[id] = top ? T(0) : ov;
+      gw[id] = ow;
+    }
+    __syncthreads();
+  }
+#undef CF_ADJ_FETCH
+#undef CF_ADJ_STORE
 }
 
 // g* = g - W G phi (weighted correction of the projection transpose);

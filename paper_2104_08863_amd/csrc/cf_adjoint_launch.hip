@@ -4,15 +4,18 @@
 
 namespace cf {
 
+// Tile: 32 x 8 columns, chunks of 32 planes (six LDS fields x three planes).
+constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 32;
+
 template <typename T>
 hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
                               const T* bu, const T* bv, const T* bw, T c1, T c2, const AdjGeo<T>& g, T nu, T s,
                               int add, T* gu, T* gv, T* gw, hipStream_t st) {
-  AdjAcc<T> X{u, v, w, au, av, aw, bu, bv, bw, c1, c2, g.g.nx, g.g.ny, g.g.nz};
-  const long n = (long)g.g.nx * g.g.ny * g.g.nz;
-  const int th = 256;
-  const long blocks = (n + th - 1) / th;
-  hipLaunchKernelGGL((k_rhs_adjoint<T>), dim3(blocks), dim3(th), 0, st, X, g, nu, s, add, gu, gv, gw);
+  AdjPtrs P{u, v, w, au, av, aw, bu, bv, bw, gu, gv, gw};
+  const long blocks = (long)((g.g.nx + ADJ_TX - 1) / ADJ_TX) * ((g.g.nz + ADJ_TZ - 1) / ADJ_TZ) *
+                      ((g.g.ny + ADJ_CY - 1) / ADJ_CY);
+  hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY>), dim3(blocks), dim3(ADJ_TX * ADJ_TZ), 0, st, P, c1,
+                     c2, g, nu, s, add);
   return hipGetLastError();
 }
 

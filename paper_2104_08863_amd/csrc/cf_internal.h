@@ -49,8 +49,6 @@ hipError_t launch_r2c_divw(int nh, const Ts* u, const Ts* v, const Ts* w, const 
                            int nz, hipStream_t s);
 
 template <typename T>
-struct AdjAcc;
-template <typename T>
 struct AdjGeo;
 
 // out = s * J_R(state)^T lam (+ A + B when add), lam = c1 A + c2 B (B may be null).

@@ -253,6 +253,7 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
 }
 
 // u1 = us - dt G p (in place on the velocity arrays); the top-wall v plane is 0.
+// One thread per point; the neighbours of p come through the caches.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_correct(T* u, T* v, T* w, const double* __restrict__ p, Geo<T> g, T dt) {

@@ -85,3 +85,44 @@ def test_mixed_projection_step():
     d0 = O.divergence(*ins, box)
     assert d1.abs().max() <= 1e-5 * d0.abs().max()
     assert bool(torch.all(v1[-1] == 0))
+
+
+def test_mixed_poisson_full_size_2048x512x1536():
+    """The Re_tau=1000-shaped mixed-precision workload at full size: after one
+    refinement pass the solution agrees with the FP64 solve of the same right-
+    hand side (itself checked against the oracle at smaller sizes) to 1e-6 and
+    satisfies the discrete equation to a small residual; mean_W(p) = 0."""
+    from paper_2104_08863_amd.api import Plan
+    wl = synth.WORKLOADS["mixed1000"]
+    yf = wl.y_faces()
+    gen = torch.Generator(device=dev())
+    gen.manual_seed(0)
+    f = torch.rand(wl.ny, wl.nz, wl.nx, dtype=torch.float64, device=dev(), generator=gen) * 2 - 1
+    pm = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="mixed", refine_passes=1)
+    p = pm.poisson_solve(f)
+    del pm
+    torch.cuda.empty_cache()
+    p64 = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64").poisson_solve(f)
+    e = float(torch.linalg.vector_norm(p - p64) / torch.linalg.vector_norm(p64))
+    print(f"mixed 2048x512x1536 vs FP64 GPU solve: rel-L2 {e:.3e}")
+    assert e <= 1e-6
+    del p64
+    torch.cuda.empty_cache()
+    # residual of L_h p = f - mean_W(f), plain torch on the GPU
+    dy = torch.tensor(np.diff(yf), device=dev())
+    yc = 0.5 * (torch.tensor(yf[1:], device=dev()) + torch.tensor(yf[:-1], device=dev()))
+    dyc = yc[1:] - yc[:-1]
+    dx, dz = wl.lx / wl.nx, wl.lz / wl.nz
+    wsum = float(dy.sum()) * wl.nx * wl.nz
+    fm = f - float((f * dy[:, None, None]).sum()) / wsum
+    # the mean line passes through FP32 storage in this mode
+    assert abs(float((p * dy[:, None, None]).sum()) / wsum) < 1e-6 * float(p.abs().max())
+    r = fm.clone()
+    r -= (torch.roll(p, -1, 2) - 2 * p + torch.roll(p, 1, 2)) / dx ** 2
+    r -= (torch.roll(p, -1, 1) - 2 * p + torch.roll(p, 1, 1)) / dz ** 2
+    fl = torch.zeros_like(p[:1])
+    flux = (p[1:] - p[:-1]) / dyc[:, None, None]
+    r -= (torch.cat([flux, fl]) - torch.cat([fl, flux])) / dy[:, None, None]
+    rel_res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(fm))
+    print(f"mixed 2048x512x1536 residual: {rel_res:.3e}")
+    assert rel_res <= 1e-5
