@@ -220,18 +220,15 @@ struct SrcDivW {
 
 // FP64 residual of the Poisson equation, r = f - L_h p (7-point staggered
 // Laplacian, no flux through the walls: a_0 = c_{ny-1} = 0), rounded to T.
-// f may be given directly or, when u != nullptr, as scale * D(u, v, w).
-template <typename T, typename Ts>
+// The right-hand side f comes from an inner source evaluated in FP64 (a plain
+// array, a divergence, or a weighted divergence).
+template <typename T, typename In>
 struct SrcResidual {
-  const double* __restrict__ f;
-  const Ts* __restrict__ u;
-  const Ts* __restrict__ v;
-  const Ts* __restrict__ w;
+  In in;
   const double* __restrict__ p;
   const double* __restrict__ a;
   const double* __restrict__ c;
-  const double* __restrict__ rdy;
-  double rdx, rdz, rdx2, rdz2, scale;
+  double rdx2, rdz2;
   int nx, ny, nz;
   __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
     const long plane = (long)nz * nx;
@@ -240,17 +237,7 @@ struct SrcResidual {
     const long rowp = ((long)j * nz + kp) * nx, rowm = ((long)j * nz + km) * nx;
     const int i0 = 2 * m, i1 = 2 * m + 1;
     const int im = (m == 0) ? nx - 1 : i0 - 1, ip = (i1 + 1 == nx) ? 0 : i1 + 1;
-    double f0, f1;
-    if (u) {
-      SrcDiv<double, Ts> d{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz};
-      const cx<double> fd = d.pair(j, k, m);
-      f0 = fd.re;
-      f1 = fd.im;
-    } else {
-      const cx<double> fp = reinterpret_cast<const cx<double>*>(f + row)[m];
-      f0 = fp.re;
-      f1 = fp.im;
-    }
+    const cx<double> fd = in.pair(j, k, m);
     const cx<double> pc = reinterpret_cast<const cx<double>*>(p + row)[m];
     const double pim = p[row + im], pip = p[row + ip];
     const cx<double> pkp = reinterpret_cast<const cx<double>*>(p + rowp)[m];
@@ -267,7 +254,7 @@ struct SrcResidual {
       l0 += a[j] * (q.re - pc.re);
       l1 += a[j] * (q.im - pc.im);
     }
-    return mk(T(f0 - l0), T(f1 - l1));
+    return mk(T(fd.re - l0), T(fd.im - l1));
   }
 };
 

@@ -88,12 +88,11 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
   }
 }
 
-template <typename T, typename Ts>
-hipError_t launch_r2c_resid(int nh, const double* f, const Ts* u, const Ts* v, const Ts* w, double scale,
-                            const double* p, const double* a, const double* c, const double* rdy,
-                            double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
-                            int ny, int nz, hipStream_t s) {
-  SrcResidual<T, Ts> src{f, u, v, w, p, a, c, rdy, rdx, rdz, rdx * rdx, rdz * rdz, scale, 2 * nh, ny, nz};
+template <typename T, typename In>
+static hipError_t r2c_resid_any(int nh, In in, const double* p, const double* a, const double* c, double rdx,
+                                double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
+                                hipStream_t s) {
+  SrcResidual<T, In> src{in, p, a, c, rdx * rdx, rdz * rdz, 2 * nh, ny, nz};
   switch (nh) {
 #define CF_CASE(N) \
   case N:          \
@@ -103,6 +102,21 @@ hipError_t launch_r2c_resid(int nh, const double* f, const Ts* u, const Ts* v, c
     default:
       return hipErrorInvalidValue;
   }
+}
+
+template <typename T, typename Ts>
+hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
+                            double scale, const double* p, const double* a, const double* c, const double* rdy,
+                            const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
+                            const cx<T>* twp, int ny, int nz, hipStream_t s) {
+  const int nx = 2 * nh;
+  if (kind == 0)
+    return r2c_resid_any<T>(nh, SrcPlain<double, double>{f, nx, nz}, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, s);
+  if (kind == 1)
+    return r2c_resid_any<T>(nh, SrcDiv<double, Ts>{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz}, p, a, c, rdx, rdz,
+                            spec, tw, twp, ny, nz, s);
+  return r2c_resid_any<T>(nh, SrcDivW<double, Ts>{u, v, w, rdy, rdyc, rdx, rdz, nx, ny, nz}, p, a, c, rdx, rdz,
+                          spec, tw, twp, ny, nz, s);
 }
 
 template <typename T, typename Ts>
@@ -181,16 +195,14 @@ hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* t
   }
 }
 
-template hipError_t launch_r2c_resid<float, double>(int, const double*, const double*, const double*,
-                                                    const double*, double, const double*, const double*,
-                                                    const double*, const double*, double, double,
-                                                    cx<float>*, const cx<float>*, const cx<float>*, int, int,
-                                                    hipStream_t);
-template hipError_t launch_r2c_resid<float, float>(int, const double*, const float*, const float*,
+template hipError_t launch_r2c_resid<float, float>(int, int, const double*, const float*, const float*,
                                                    const float*, double, const double*, const double*,
-                                                   const double*, const double*, double, double,
+                                                   const double*, const double*, const double*, double, double,
                                                    cx<float>*, const cx<float>*, const cx<float>*, int, int,
                                                    hipStream_t);
+template hipError_t launch_r2c_divw<float, float>(int, const float*, const float*, const float*, const double*,
+                                                  const double*, double, double, cx<float>*, const cx<float>*,
+                                                  const cx<float>*, int, int, hipStream_t);
 template hipError_t launch_r2c_div_t<float, float>(int, const float*, const float*, const float*,
                                                    const double*, double, double, double, cx<float>*,
                                                    const cx<float>*, const cx<float>*, int, int, hipStream_t);

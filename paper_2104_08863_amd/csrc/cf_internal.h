@@ -28,13 +28,13 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
                           const double* rdy, double rdx, double rdz, double scale, cx<T>* spec,
                           const cx<T>* tw, const cx<T>* twp, int ny, int nz, hipStream_t s);
 
-// Forward real transform of the FP64 residual f - L_h p, with f given or (u
-// non-null) f = scale * D(u, v, w).
+// Forward real transform of the FP64 residual f - L_h p with f = the array f
+// (kind 0), scale * D(u, v, w) (kind 1) or D(u / W, v / W, w / W) (kind 2).
 template <typename T, typename Ts>
-hipError_t launch_r2c_resid(int nh, const double* f, const Ts* u, const Ts* v, const Ts* w, double scale,
-                            const double* p, const double* a, const double* c, const double* rdy,
-                            double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp,
-                            int ny, int nz, hipStream_t s);
+hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
+                            double scale, const double* p, const double* a, const double* c, const double* rdy,
+                            const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
+                            const cx<T>* twp, int ny, int nz, hipStream_t s);
 
 // Divergence fused into the forward real transform, velocity type Ts.
 template <typename T, typename Ts>

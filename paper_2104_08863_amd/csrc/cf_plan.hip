@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -286,6 +287,13 @@ struct Tabs<float> {
 
 // f (physical) -> spectrum in layout B
 template <typename T>
+const cf::AdjGeo<T>& adj_geo(const cf_plan* pl);
+template <>
+const cf::AdjGeo<double>& adj_geo<double>(const cf_plan* pl) { return pl->a64; }
+template <>
+const cf::AdjGeo<float>& adj_geo<float>(const cf_plan* pl) { return pl->a32; }
+
+template <typename T>
 cf_status forward_t(cf_plan* pl, const double* f, cx<T>* outB, hipStream_t s) {
   using TB = Tabs<T>;
   cx<T>* A = static_cast<cx<T>*>(pl->specA);
@@ -369,41 +377,52 @@ cf_status poisson_t(cf_plan* pl, const double* f, double* p, hipStream_t s) {
   return CF_OK;
 }
 
+// Right-hand side of a mixed-precision solve: an FP64 array f (kind 0),
+// scale * D(u, v, w) (kind 1) or D(u / W, v / W, w / W) (kind 2, the
+// transposed projection), with float velocities.
+struct MixedRhs {
+  int kind;
+  const double* f;
+  const float *u, *v, *w;
+  double scale;
+};
+
 // Mixed-precision Poisson solve: p0 = S32(f), then refine_passes times
 // p += S32(f - L_h p) with the residual formed in FP64.  S32 runs the transforms
-// and the bulk PDD in FP32 and the FP64 line set in FP64.  When `u` is
-// non-null the right-hand side is scale * D(u, v, w) (float velocities).
-cf_status poisson_mixed(cf_plan* pl, const double* f, const float* u, const float* v, const float* w,
-                        double scale, double* p, hipStream_t s) {
+// and the bulk PDD in FP32 and the FP64 line set in FP64.
+cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
   using TB = Tabs<float>;
   cx<float>* A = static_cast<cx<float>*>(pl->specA);
   cx<float>* B = static_cast<cx<float>*>(pl->specB);
-  const double* fsrc = f;
-  if (!u && f == p && pl->opt.refine_passes > 0) {
-    CF_HIP(hipMemcpyAsync(pl->fws, f, sizeof(double) * (size_t)pl->nx * pl->ny * pl->nz,
+  if (rhs.kind == 0 && rhs.f == p && pl->opt.refine_passes > 0) {
+    CF_HIP(hipMemcpyAsync(pl->fws, rhs.f, sizeof(double) * (size_t)pl->nx * pl->ny * pl->nz,
                           hipMemcpyDeviceToDevice, s),
            "hipMemcpyAsync");
-    fsrc = pl->fws;
+    rhs.f = pl->fws;
   }
-  if (u) {
+  if (rhs.kind == 0) {
+    CF_TRY(forward_t<float>(pl, rhs.f, B, s));
+  } else {
     CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+div launch", [&] {
-      return cf::launch_r2c_div_t<float, float>(pl->nh, u, v, w, pl->d_rdy, 1.0 / pl->dx, 1.0 / pl->dz, scale, A,
-                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+      if (rhs.kind == 1)
+        return cf::launch_r2c_div_t<float, float>(pl->nh, rhs.u, rhs.v, rhs.w, pl->d_rdy, 1.0 / pl->dx,
+                                                  1.0 / pl->dz, rhs.scale, A, TB::twx(pl), TB::twp(pl), pl->ny,
+                                                  pl->nz, s);
+      return cf::launch_r2c_divw<float, float>(pl->nh, rhs.u, rhs.v, rhs.w, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx,
+                                               1.0 / pl->dz, A, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
     }));
     CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
       return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
     }));
-  } else {
-    CF_TRY(forward_t<float>(pl, fsrc, B, s));
   }
   CF_TRY(solve_t<float>(pl, B, B, s));
   CF_TRY(inverse_t<float>(pl, B, p, s));
   const float scl = float(1.0 / ((double)pl->nx * (double)pl->nz));
   for (int it = 0; it < pl->opt.refine_passes; ++it) {
     CF_TRY(timed(pl, CF_K_R2C_X, s, "residual r2c launch", [&] {
-      return cf::launch_r2c_resid<float, float>(pl->nh, fsrc, u, v, w, scale, p, pl->d_a, pl->d_c, pl->d_rdy,
-                                                1.0 / pl->dx, 1.0 / pl->dz, A, TB::twx(pl), TB::twp(pl),
-                                                pl->ny, pl->nz, s);
+      return cf::launch_r2c_resid<float, float>(rhs.kind, pl->nh, rhs.f, rhs.u, rhs.v, rhs.w, rhs.scale, p, pl->d_a,
+                                                pl->d_c, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx, 1.0 / pl->dz, A,
+                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
     }));
     CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
       return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
@@ -433,7 +452,7 @@ cf_status step_mixed(cf_plan* pl, const float* u, const float* v, const float* w
   CF_TRY(timed(pl, CF_K_RK2, s, "rk stage 2", [&] {
     return cf::launch_rk_stage<float>(2, ub, vb, wb, u, v, w, u1, v1, w1, pl->g32, fdt, fnu, ffx, s);
   }));
-  CF_TRY(poisson_mixed(pl, nullptr, u1, v1, w1, 1.0 / dt, pp, s));
+  CF_TRY(poisson_mixed(pl, MixedRhs{1, nullptr, u1, v1, w1, 1.0 / dt}, pp, s));
   CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
     return cf::launch_correct<float>(u1, v1, w1, pp, pl->g32, fdt, s);
   }));
@@ -463,47 +482,55 @@ cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w,
   return CF_OK;
 }
 
-// Adjoint of one FP64 projection step.
-cf_status step_adjoint64(cf_plan* pl, const double* u, const double* v, const double* w, const double* g1u,
-                         const double* g1v, const double* g1w, double* gu, double* gv, double* gw, double dt,
-                         double nu, double fx, hipStream_t s) {
-  double* ub = static_cast<double*>(pl->ub);
-  double* vb = static_cast<double*>(pl->vb);
-  double* wb = static_cast<double*>(pl->wb);
-  double* su = static_cast<double*>(pl->gsu);
-  double* sv = static_cast<double*>(pl->gsv);
-  double* sw = static_cast<double*>(pl->gsw);
-  double* bu = static_cast<double*>(pl->gbu);
-  double* bv = static_cast<double*>(pl->gbv);
-  double* bw = static_cast<double*>(pl->gbw);
-  // recompute the stage-1 field
-  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
-    return cf::launch_rk_stage<double>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g64, dt, nu, fx, s);
-  }));
+// Adjoint of one projection step, state type T.  The transposed projection
+// runs first: its spectral workspace shares memory with the stage-1 fields,
+// which are recomputed afterwards; the pressure workspace shares memory with gb.
+template <typename T>
+cf_status step_adjoint_t(cf_plan* pl, const T* u, const T* v, const T* w, const T* g1u, const T* g1v,
+                         const T* g1w, T* gu, T* gv, T* gw, double dt, double nu, double fx, hipStream_t s) {
+  T* ub = static_cast<T*>(pl->ub);
+  T* vb = static_cast<T*>(pl->vb);
+  T* wb = static_cast<T*>(pl->wb);
+  T* su = static_cast<T*>(pl->gsu);
+  T* sv = static_cast<T*>(pl->gsv);
+  T* sw = static_cast<T*>(pl->gsw);
+  T* bu = static_cast<T*>(pl->gbu);
+  T* bv = static_cast<T*>(pl->gbv);
+  T* bw = static_cast<T*>(pl->gbw);
+  const T tdt = T(dt), tnu = T(nu), tfx = T(fx);
   // g* = g1 - W G L^+ D (g1 / W)
-  cx<double>* A = static_cast<cx<double>*>(pl->specA);
-  cx<double>* B = static_cast<cx<double>*>(pl->specB);
-  CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+weighted div launch", [&] {
-    return cf::launch_r2c_divw<double, double>(pl->nh, g1u, g1v, g1w, pl->d_rdy, pl->g64.rdyc, 1.0 / pl->dx,
-                                               1.0 / pl->dz, A, pl->tw_x64, pl->twp64, pl->ny, pl->nz, s);
-  }));
-  CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
-    return cf::launch_fft_z<double>(pl->nz, false, A, B, pl->tw_z64, pl->ny, pl->nkx, s);
-  }));
-  CF_TRY(solve_t<double>(pl, B, B, s));
-  CF_TRY(inverse_t<double>(pl, B, pl->pws, s));
+  if constexpr (std::is_same<T, double>::value) {
+    cx<double>* A = static_cast<cx<double>*>(pl->specA);
+    cx<double>* B = static_cast<cx<double>*>(pl->specB);
+    CF_TRY(timed(pl, CF_K_R2C_X, s, "r2c+weighted div launch", [&] {
+      return cf::launch_r2c_divw<double, double>(pl->nh, g1u, g1v, g1w, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx,
+                                                 1.0 / pl->dz, A, pl->tw_x64, pl->twp64, pl->ny, pl->nz, s);
+    }));
+    CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
+      return cf::launch_fft_z<double>(pl->nz, false, A, B, pl->tw_z64, pl->ny, pl->nkx, s);
+    }));
+    CF_TRY(solve_t<double>(pl, B, B, s));
+    CF_TRY(inverse_t<double>(pl, B, pl->pws, s));
+  } else {
+    CF_TRY(poisson_mixed(pl, MixedRhs{2, nullptr, g1u, g1v, g1w, 1.0}, pl->pws, s));
+  }
+  const cf::AdjGeo<T>& ag = adj_geo<T>(pl);
   CF_TRY(timed(pl, CF_K_ADJ_CORRECT, s, "weighted correction", [&] {
-    return cf::launch_correct_w<double>(g1u, g1v, g1w, su, sv, sw, pl->pws, pl->a64, s);
+    return cf::launch_correct_w<T>(g1u, g1v, g1w, su, sv, sw, pl->pws, ag, s);
   }));
-  // gb = dt/2 J_R(ub)^T g*
+  // recompute the stage-1 field (overwrites the spectral workspace)
+  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
+    return cf::launch_rk_stage<T>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, ag.g, tdt, tnu, tfx, s);
+  }));
+  // gb = dt/2 J_R(ub)^T g*   (overwrites the pressure workspace)
   CF_TRY(timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
-    return cf::launch_rhs_adjoint<double>(ub, vb, wb, su, sv, sw, nullptr, nullptr, nullptr, 1.0, 0.0, pl->a64, nu,
-                                          0.5 * dt, 0, bu, bv, bw, s);
+    return cf::launch_rhs_adjoint<T>(ub, vb, wb, su, sv, sw, nullptr, nullptr, nullptr, T(1), T(0), ag, tnu,
+                                     T(0.5) * tdt, 0, bu, bv, bw, s);
   }));
   // g = g* + gb + J_R(u)^T (dt/2 g* + dt gb)
   CF_TRY(timed(pl, CF_K_ADJ_RHS, s, "rhs adjoint", [&] {
-    return cf::launch_rhs_adjoint<double>(u, v, w, su, sv, sw, bu, bv, bw, 0.5 * dt, dt, pl->a64, nu, 1.0, 1, gu, gv,
-                                          gw, s);
+    return cf::launch_rhs_adjoint<T>(u, v, w, su, sv, sw, bu, bv, bw, T(0.5) * tdt, tdt, ag, tnu, T(1), 1, gu, gv,
+                                     gw, s);
   }));
   return CF_OK;
 }
@@ -748,42 +775,47 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     pl->a64 = cf::AdjGeo<double>{pl->g64, pl->d_dy, pl->d_dyc, pl->d_rdyc};
     pl->a32 = cf::AdjGeo<float>{pl->g32, pl->s_dy, pl->s_dyc, pl->s_rdyc};
   }
-  if (opt.precision == CF_MIXED && opt.refine_passes > 0) {
-    if ((st = dalloc(pl, &pl->fws, (size_t)nx * ny * nz)) != CF_OK) return bail(st);
-  }
+  // Workspace.  Step plans: the stage-1 fields and the two spectral buffers
+  // share one block (the stage-1 fields are dead while the pressure is solved);
+  // adjoint plans: the pressure shares the block of gb.  The FP64 copy of f a
+  // mixed solve needs when p aliases f is the pressure workspace of step plans.
+  const size_t npts = (size_t)nx * ny * nz;
+  const size_t es = (opt.precision == CF_FP64) ? sizeof(double) : sizeof(float);
+  const size_t ecs = 2 * es;
+  const size_t nspec = (size_t)ny * pl->nkx * nz;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t field_b = al(npts * es), spec_b = al(nspec * ecs);
   if (opt.flags & CF_PLAN_STEP) {
-    const size_t npts = (size_t)nx * ny * nz;
-    if (opt.precision == CF_FP64) {
-      double *a = nullptr, *b = nullptr, *c = nullptr;
-      if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
-      if ((st = dalloc(pl, &b, npts)) != CF_OK) return bail(st);
-      if ((st = dalloc(pl, &c, npts)) != CF_OK) return bail(st);
-      pl->ub = a;
-      pl->vb = b;
-      pl->wb = c;
-    } else {
-      float *a = nullptr, *b = nullptr, *c = nullptr;
-      if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
-      if ((st = dalloc(pl, &b, npts)) != CF_OK) return bail(st);
-      if ((st = dalloc(pl, &c, npts)) != CF_OK) return bail(st);
-      pl->ub = a;
-      pl->vb = b;
-      pl->wb = c;
-    }
-    if ((st = dalloc(pl, &pl->pws, npts)) != CF_OK) return bail(st);
+    unsigned char* blk = nullptr;
+    if ((st = dalloc(pl, &blk, std::max(3 * field_b, 2 * spec_b))) != CF_OK) return bail(st);
+    pl->ub = blk;
+    pl->vb = blk + field_b;
+    pl->wb = blk + 2 * field_b;
+    pl->specA = blk;
+    pl->specB = blk + spec_b;
     if (opt.flags & CF_PLAN_ADJOINT) {
-      void** slots[6] = {&pl->gsu, &pl->gsv, &pl->gsw, &pl->gbu, &pl->gbv, &pl->gbw};
-      for (void** sl : slots) {
-        if (opt.precision == CF_FP64) {
-          double* a = nullptr;
-          if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
-          *sl = a;
-        } else {
-          float* a = nullptr;
-          if ((st = dalloc(pl, &a, npts)) != CF_OK) return bail(st);
-          *sl = a;
-        }
-      }
+      unsigned char *gs = nullptr, *gb = nullptr;
+      if ((st = dalloc(pl, &gs, 3 * field_b)) != CF_OK) return bail(st);
+      if ((st = dalloc(pl, &gb, std::max(3 * field_b, al(npts * sizeof(double))))) != CF_OK) return bail(st);
+      pl->gsu = gs;
+      pl->gsv = gs + field_b;
+      pl->gsw = gs + 2 * field_b;
+      pl->gbu = gb;
+      pl->gbv = gb + field_b;
+      pl->gbw = gb + 2 * field_b;
+      pl->pws = reinterpret_cast<double*>(gb);
+    } else {
+      if ((st = dalloc(pl, &pl->pws, npts)) != CF_OK) return bail(st);
+    }
+    pl->fws = pl->pws;
+  } else {
+    unsigned char *a = nullptr, *b = nullptr;
+    if ((st = dalloc(pl, &a, spec_b)) != CF_OK) return bail(st);
+    if ((st = dalloc(pl, &b, spec_b)) != CF_OK) return bail(st);
+    pl->specA = a;
+    pl->specB = b;
+    if (opt.precision == CF_MIXED && opt.refine_passes > 0) {
+      if ((st = dalloc(pl, &pl->fws, npts)) != CF_OK) return bail(st);
     }
   }
   if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
@@ -793,20 +825,6 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
       special_factors(pl, pl->special[l], den.data() + l * ny, cpv.data() + l * ny);
     if ((st = upload(pl, &pl->d_special_den, den)) != CF_OK) return bail(st);
     if ((st = upload(pl, &pl->d_special_cp, cpv)) != CF_OK) return bail(st);
-  }
-  const size_t nspec = (size_t)ny * pl->nkx * nz;
-  if (opt.precision == CF_FP64) {
-    cx<double>*a = nullptr, *b = nullptr;
-    if ((st = dalloc(pl, &a, nspec)) != CF_OK) return bail(st);
-    if ((st = dalloc(pl, &b, nspec)) != CF_OK) return bail(st);
-    pl->specA = a;
-    pl->specB = b;
-  } else {
-    cx<float>*a = nullptr, *b = nullptr;
-    if ((st = dalloc(pl, &a, nspec)) != CF_OK) return bail(st);
-    if ((st = dalloc(pl, &b, nspec)) != CF_OK) return bail(st);
-    pl->specA = a;
-    pl->specB = b;
   }
   *out = pl;
   return CF_OK;
@@ -868,7 +886,7 @@ cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream
   CF_TRY(check_ptr(f, "f"));
   CF_TRY(check_ptr(p, "p"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (pl->mixed()) return poisson_mixed(pl, f, nullptr, nullptr, nullptr, 1.0, p, s);
+  if (pl->mixed()) return poisson_mixed(pl, MixedRhs{0, f, nullptr, nullptr, nullptr, 1.0}, p, s);
   return poisson_t<double>(pl, f, p, s);
 }
 
@@ -923,11 +941,15 @@ cf_status cf_projection_step_adjoint(cf_plan* pl, const void* u, const void* v, 
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
   if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (pl->mixed()) return fail(CF_ERR_UNSUPPORTED, "mixed-precision adjoint is not built yet");
-  return step_adjoint64(pl, static_cast<const double*>(u), static_cast<const double*>(v),
-                        static_cast<const double*>(w), static_cast<const double*>(gu1), static_cast<const double*>(gv1),
-                        static_cast<const double*>(gw1), static_cast<double*>(gu), static_cast<double*>(gv),
-                        static_cast<double*>(gw), dt, nu, fx, s);
+  if (pl->mixed())
+    return step_adjoint_t<float>(pl, static_cast<const float*>(u), static_cast<const float*>(v),
+                                 static_cast<const float*>(w), static_cast<const float*>(gu1),
+                                 static_cast<const float*>(gv1), static_cast<const float*>(gw1),
+                                 static_cast<float*>(gu), static_cast<float*>(gv), static_cast<float*>(gw), dt, nu, fx, s);
+  return step_adjoint_t<double>(pl, static_cast<const double*>(u), static_cast<const double*>(v),
+                                static_cast<const double*>(w), static_cast<const double*>(gu1),
+                                static_cast<const double*>(gv1), static_cast<const double*>(gw1),
+                                static_cast<double*>(gu), static_cast<double*>(gv), static_cast<double*>(gw), dt, nu, fx, s);
 }
 
 cf_status cf_rhs_adjoint(cf_plan* pl, const void* u, const void* v, const void* w, const void* lu, const void* lv,
