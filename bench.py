@@ -162,6 +162,36 @@ def secondary(wl, steps):
         "input": "uniform[-1,1] RHS from a seeded torch CUDA generator"}
     del pm, pb, fb
     torch.cuda.empty_cache()
+    # mixed-precision forward + adjoint step on the Re_tau=2000-shaped grid
+    # (FP32 state; the gradient overwrites the incoming adjoint field)
+    c5 = synth.WORKLOADS["adj2000"]
+    n5 = c5.nx * c5.ny * c5.nz
+    y5 = c5.y_faces()
+    yc = torch.tensor(0.5 * (y5[1:] + y5[:-1]), dtype=torch.float32, device=dev)
+    gen.manual_seed(0)
+    shp = (c5.ny, c5.nz, c5.nx)
+
+    def gauss():
+        return torch.randn(shp, dtype=torch.float32, device=dev, generator=gen) * 0.1
+    u = gauss() + (1.5 * (1 - yc * yc))[:, None, None]
+    v = gauss()
+    v[-1] = 0
+    w = gauss()
+    o = tuple(torch.empty_like(u) for _ in range(3))
+    g = (gauss(), gauss(), gauss())
+    pm = Plan(c5.nx, c5.ny, c5.nz, c5.lx, c5.lz, y5, precision="mixed", adjoint=True)
+
+    def fwd_adj5():
+        pm.projection_step(u, v, w, c5.dt, c5.nu, c5.fx, out=o)
+        pm.projection_step_adjoint(u, v, w, *g, c5.dt, c5.nu, c5.fx, out=g)
+    t = _time(fwd_adj5, 2, warmup=1)
+    finite = bool(torch.isfinite(g[0]).all() and torch.isfinite(o[0]).all())
+    res["fwd_adjoint_step_mixed_2048x768x2048"] = {
+        "grid": [c5.nx, c5.ny, c5.nz], "ms": round(t * 1e3, 2), "Mpts_s": round(n5 / t / 1e6, 1),
+        "finite": finite, "plan_workspace_GB": round(pm.info()["workspace_bytes"] / 1e9, 1),
+        "input": "perturbed Poiseuille (seeded torch CUDA generator), FP32 state"}
+    del pm, u, v, w, o, g
+    torch.cuda.empty_cache()
     return res
 
 
