@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--workload", default="step550")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--secondary-steps", type=int, default=6,
-                    help="timed calls per secondary figure (Poisson FP64/mixed, fwd+adjoint)")
+                    help="timed calls per secondary figure (Poisson FP64/mixed, fwd+adjoint); 0 skips them")
     ap.add_argument("--poisson-only", action="store_true",
                     help="time the Poisson solve alone instead of the projection step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -307,7 +307,7 @@ def main():
         "model_GBps_whole_step": round(model_bytes / (ms * 1e-3) / 1e9, 1),
         "kernels": per_kernel,
     }
-    if not args.poisson_only:
+    if not args.poisson_only and args.secondary_steps > 0:
         del u, v, w, outs, p, plan
         torch.cuda.empty_cache()
         out["also"] = secondary(wl, args.secondary_steps)

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libchanflow.so")
+# CHANFLOW_LIB may point at another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("CHANFLOW_LIB") or os.path.join(PKG, "libchanflow.so")
 HOSTLIB_PATH = os.path.join(PKG, "libchanflow_host.so")
 
 CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMERIC = range(6)

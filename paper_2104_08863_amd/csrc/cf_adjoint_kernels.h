@@ -42,8 +42,17 @@ struct AdjOut {
   T gu, gv, gw;
 };
 
+// Lower-face terms of plane j that equal upper-face terms of plane j-1: the
+// x-y and y-z edge factors mu * A(v) at face j (before the wl/wu weight) and
+// the centre term vc * xi_y at centre j.
+template <typename T>
+struct AdjCarry {
+  T exy, eyz, cy;
+};
+
 template <typename T, class Acc>
-__device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGeo<T>& G, int j, T nu) {
+__device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGeo<T>& G, int j, T nu,
+                                                       bool have, AdjCarry<T> below, AdjCarry<T>& above) {
   const Geo<T>& g = G.g;
   const int ny = g.ny;
   const T h = T(0.5);
@@ -60,13 +69,21 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
     const T xi0 = (A.LU(0, 0, -1) - A.LU(0, 0, 0)) * rdx;
     const T xi1 = (A.LU(0, 0, 0) - A.LU(0, 0, 1)) * rdx;
     T acc = uc0 * xi0 + uc1 * xi1;
+    above.exy = T(0);
     if (!top) {
       const T mu = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
-      acc += mu * (h * (A.V(0, 0, 0) + A.V(0, 0, 1))) * g.wl[j];
+      above.exy = mu * (h * (A.V(0, 0, 0) + A.V(0, 0, 1)));
+      acc += above.exy * g.wl[j];
     }
     if (!bot) {
-      const T mu = A.LU(-1, 0, 0) * rym - A.LU(0, 0, 0) * ry0 + (A.LV(-1, 0, 0) - A.LV(-1, 0, 1)) * rdx;
-      acc += mu * (h * (A.V(-1, 0, 0) + A.V(-1, 0, 1))) * g.wu[j - 1];
+      T e;
+      if (have) {
+        e = below.exy;
+      } else {
+        const T mu = A.LU(-1, 0, 0) * rym - A.LU(0, 0, 0) * ry0 + (A.LV(-1, 0, 0) - A.LV(-1, 0, 1)) * rdx;
+        e = mu * (h * (A.V(-1, 0, 0) + A.V(-1, 0, 1)));
+      }
+      acc += e * g.wu[j - 1];
     }
     {
       const T mk0 = (A.LU(0, 0, 0) - A.LU(0, 1, 0)) * rdz + (A.LW(0, 0, 0) - A.LW(0, 0, 1)) * rdx;
@@ -93,13 +110,21 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
       const T m1 = (A.LU(0, 0, -1) - A.LU(0, 1, -1)) * rdz + (A.LW(0, 0, -1) - A.LW(0, 0, 0)) * rdx;
       acc += h * (m0 * (h * (A.U(0, 0, 0) + A.U(0, 1, 0))) + m1 * (h * (A.U(0, 0, -1) + A.U(0, 1, -1))));
     }
+    above.eyz = T(0);
     if (!top) {
       const T mu = (A.LV(0, 0, 0) - A.LV(0, 1, 0)) * rdz + A.LW(0, 0, 0) * ry0 - A.LW(1, 0, 0) * ryp;
-      acc += mu * (h * (A.V(0, 0, 0) + A.V(0, 1, 0))) * g.wl[j];
+      above.eyz = mu * (h * (A.V(0, 0, 0) + A.V(0, 1, 0)));
+      acc += above.eyz * g.wl[j];
     }
     if (!bot) {
-      const T mu = (A.LV(-1, 0, 0) - A.LV(-1, 1, 0)) * rdz + A.LW(-1, 0, 0) * rym - A.LW(0, 0, 0) * ry0;
-      acc += mu * (h * (A.V(-1, 0, 0) + A.V(-1, 1, 0))) * g.wu[j - 1];
+      T e;
+      if (have) {
+        e = below.eyz;
+      } else {
+        const T mu = (A.LV(-1, 0, 0) - A.LV(-1, 1, 0)) * rdz + A.LW(-1, 0, 0) * rym - A.LW(0, 0, 0) * ry0;
+        e = mu * (h * (A.V(-1, 0, 0) + A.V(-1, 1, 0)));
+      }
+      acc += e * g.wu[j - 1];
     }
     const T l0 = A.LW(0, 0, 0);
     T lap = (A.LW(0, 0, 1) - T(2) * l0 + A.LW(0, 0, -1)) * g.rdx2 + (A.LW(0, 1, 0) - T(2) * l0 + A.LW(0, -1, 0)) * g.rdz2;
@@ -111,15 +136,21 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
   }
   // ---------------- v point (i, face j+1, k), interior faces only
   o.gv = T(0);
+  above.cy = T(0);
   if (!top) {
     const T rc0 = G.rdyc[j];
     const T rcm = bot ? T(0) : G.rdyc[j - 1];
     const T rcp = (j + 1 < ny - 1) ? G.rdyc[j + 1] : T(0);
-    const T vc0 = h * (A.V(0, 0, 0) + A.V(-1, 0, 0));
+    T c0;
+    if (have) {
+      c0 = below.cy;
+    } else {
+      const T vc0 = h * (A.V(0, 0, 0) + A.V(-1, 0, 0));
+      c0 = vc0 * (A.LV(-1, 0, 0) * rcm - A.LV(0, 0, 0) * rc0);
+    }
     const T vc1 = h * (A.V(1, 0, 0) + A.V(0, 0, 0));
-    const T xi0 = A.LV(-1, 0, 0) * rcm - A.LV(0, 0, 0) * rc0;
-    const T xi1 = A.LV(0, 0, 0) * rc0 - A.LV(1, 0, 0) * rcp;
-    T acc = vc0 * xi0 + vc1 * xi1;
+    above.cy = vc1 * (A.LV(0, 0, 0) * rc0 - A.LV(1, 0, 0) * rcp);
+    T acc = c0 + above.cy;
     const T a = g.wl[j], b = g.wu[j];
     {
       const T m0 = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
@@ -243,6 +274,8 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
   T* gu = static_cast<T*>(P.gu);
   T* gv = static_cast<T*>(P.gv);
   T* gw = static_cast<T*>(P.gw);
+  AdjCarry<T> carry{T(0), T(0), T(0)};
+  bool have = false;
   for (int j = j0; j < j1; ++j) {
     CF_ADJ_STORE((j + 1) % 3)
     __syncthreads();
@@ -251,7 +284,10 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
     A.s0 = (j % 3) * PLANE;
     A.sp = ((j + 1) % 3) * PLANE;
     if (mine) {
-      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, j, nu);
+      AdjCarry<T> up;
+      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, j, nu, have, carry, up);
+      carry = up;
+      have = true;
       const long id = (long)j * plane + pid;
       const bool top = (j == ny - 1);
       T ou = s * o.gu, ov = s * o.gv, ow = s * o.gw;

@@ -4,8 +4,8 @@
 
 namespace cf {
 
-// Tile: 32 x 8 columns, chunks of 32 planes (six LDS fields x three planes).
-constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 32;
+// Tile: 32 x 8 columns, chunks of 64 planes (six LDS fields x three planes).
+constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 64;
 
 template <typename T>
 hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
