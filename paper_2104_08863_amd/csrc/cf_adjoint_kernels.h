@@ -51,16 +51,16 @@ struct AdjCarry {
 };
 
 template <typename T, class Acc>
-__device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGeo<T>& G, int j, T nu,
-                                                       bool have, AdjCarry<T> below, AdjCarry<T>& above) {
+__device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGeo<T>& G, const YTab<T>& Y, int j,
+                                                       T nu, bool have, AdjCarry<T> below, AdjCarry<T>& above) {
   const Geo<T>& g = G.g;
   const int ny = g.ny;
   const T h = T(0.5);
   const T rdx = g.rdx, rdz = g.rdz;
   const bool top = (j == ny - 1), bot = (j == 0);
-  const T ry0 = g.rdy[j];
-  const T ryp = top ? T(0) : g.rdy[j + 1];
-  const T rym = bot ? T(0) : g.rdy[j - 1];
+  const T ry0 = Y.rdy(j);
+  const T ryp = top ? T(0) : Y.rdy(j + 1);
+  const T rym = bot ? T(0) : Y.rdy(j - 1);
   AdjOut<T> o;
   // ---------------- u point (i+1/2, j, k)
   {
@@ -73,7 +73,7 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
     if (!top) {
       const T mu = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
       above.exy = mu * (h * (A.V(0, 0, 0) + A.V(0, 0, 1)));
-      acc += above.exy * g.wl[j];
+      acc += above.exy * Y.wl(j);
     }
     if (!bot) {
       T e;
@@ -83,7 +83,7 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
         const T mu = A.LU(-1, 0, 0) * rym - A.LU(0, 0, 0) * ry0 + (A.LV(-1, 0, 0) - A.LV(-1, 0, 1)) * rdx;
         e = mu * (h * (A.V(-1, 0, 0) + A.V(-1, 0, 1)));
       }
-      acc += e * g.wu[j - 1];
+      acc += e * Y.wu(j - 1);
     }
     {
       const T mk0 = (A.LU(0, 0, 0) - A.LU(0, 1, 0)) * rdz + (A.LW(0, 0, 0) - A.LW(0, 0, 1)) * rdx;
@@ -93,8 +93,8 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
     const T l0 = A.LU(0, 0, 0);
     T lap = (A.LU(0, 0, 1) - T(2) * l0 + A.LU(0, 0, -1)) * g.rdx2 + (A.LU(0, 1, 0) - T(2) * l0 + A.LU(0, -1, 0)) * g.rdz2;
     const T q0 = l0 * ry0;
-    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (A.LU(1, 0, 0) * ryp - q0) * g.rdyc[j];
-    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - A.LU(-1, 0, 0) * rym) * g.rdyc[j - 1];
+    const T ft = top ? -T(2) * q0 * Y.rdy_top : (A.LU(1, 0, 0) * ryp - q0) * Y.rdyc(j);
+    const T fb = bot ? T(2) * q0 * Y.rdy_bot : (q0 - A.LU(-1, 0, 0) * rym) * Y.rdyc(j - 1);
     lap += ft - fb;
     o.gu = -acc + nu * lap;
   }
@@ -114,7 +114,7 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
     if (!top) {
       const T mu = (A.LV(0, 0, 0) - A.LV(0, 1, 0)) * rdz + A.LW(0, 0, 0) * ry0 - A.LW(1, 0, 0) * ryp;
       above.eyz = mu * (h * (A.V(0, 0, 0) + A.V(0, 1, 0)));
-      acc += above.eyz * g.wl[j];
+      acc += above.eyz * Y.wl(j);
     }
     if (!bot) {
       T e;
@@ -124,13 +124,13 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
         const T mu = (A.LV(-1, 0, 0) - A.LV(-1, 1, 0)) * rdz + A.LW(-1, 0, 0) * rym - A.LW(0, 0, 0) * ry0;
         e = mu * (h * (A.V(-1, 0, 0) + A.V(-1, 1, 0)));
       }
-      acc += e * g.wu[j - 1];
+      acc += e * Y.wu(j - 1);
     }
     const T l0 = A.LW(0, 0, 0);
     T lap = (A.LW(0, 0, 1) - T(2) * l0 + A.LW(0, 0, -1)) * g.rdx2 + (A.LW(0, 1, 0) - T(2) * l0 + A.LW(0, -1, 0)) * g.rdz2;
     const T q0 = l0 * ry0;
-    const T ft = top ? -T(2) * q0 * g.rdy[ny - 1] : (A.LW(1, 0, 0) * ryp - q0) * g.rdyc[j];
-    const T fb = bot ? T(2) * q0 * g.rdy[0] : (q0 - A.LW(-1, 0, 0) * rym) * g.rdyc[j - 1];
+    const T ft = top ? -T(2) * q0 * Y.rdy_top : (A.LW(1, 0, 0) * ryp - q0) * Y.rdyc(j);
+    const T fb = bot ? T(2) * q0 * Y.rdy_bot : (q0 - A.LW(-1, 0, 0) * rym) * Y.rdyc(j - 1);
     lap += ft - fb;
     o.gw = -acc + nu * lap;
   }
@@ -138,9 +138,9 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
   o.gv = T(0);
   above.cy = T(0);
   if (!top) {
-    const T rc0 = G.rdyc[j];
-    const T rcm = bot ? T(0) : G.rdyc[j - 1];
-    const T rcp = (j + 1 < ny - 1) ? G.rdyc[j + 1] : T(0);
+    const T rc0 = Y.rdyc(j);
+    const T rcm = bot ? T(0) : Y.rdyc(j - 1);
+    const T rcp = (j + 1 < ny - 1) ? Y.rdyc(j + 1) : T(0);
     T c0;
     if (have) {
       c0 = below.cy;
@@ -151,7 +151,7 @@ __device__ __forceinline__ AdjOut<T> rhs_adjoint_point(const Acc& A, const AdjGe
     const T vc1 = h * (A.V(1, 0, 0) + A.V(0, 0, 0));
     above.cy = vc1 * (A.LV(0, 0, 0) * rc0 - A.LV(1, 0, 0) * rcp);
     T acc = c0 + above.cy;
-    const T a = g.wl[j], b = g.wu[j];
+    const T a = Y.wl(j), b = Y.wu(j);
     {
       const T m0 = A.LU(0, 0, 0) * ry0 - A.LU(1, 0, 0) * ryp + (A.LV(0, 0, 0) - A.LV(0, 0, 1)) * rdx;
       const T m1 = A.LU(0, 0, -1) * ry0 - A.LU(1, 0, -1) * ryp + (A.LV(0, 0, -1) - A.LV(0, 0, 0)) * rdx;
@@ -206,6 +206,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
   constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, TH = TX * TZ;
   constexpr int PER = (PLANE + TH - 1) / TH;
   __shared__ T sm[6 * 3 * PLANE];
+  __shared__ T sy[4 * (CY + 2)];
   const T* u = static_cast<const T*>(P.u);
   const T* v = static_cast<const T*>(P.v);
   const T* w = static_cast<const T*>(P.w);
@@ -274,6 +275,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
   T* gu = static_cast<T*>(P.gu);
   T* gv = static_cast<T*>(P.gv);
   T* gw = static_cast<T*>(P.gw);
+  const YTab<T> Y = ytab_fill(sy, CY + 2, j0 - 1, g);
   AdjCarry<T> carry{T(0), T(0), T(0)};
   bool have = false;
   for (int j = j0; j < j1; ++j) {
@@ -285,7 +287,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
     A.sp = ((j + 1) % 3) * PLANE;
     if (mine) {
       AdjCarry<T> up;
-      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, j, nu, have, carry, up);
+      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, Y, j, nu, have, carry, up);
       carry = up;
       have = true;
       const long id = (long)j * plane + pid;

@@ -28,6 +28,38 @@ struct Geo {
   int nx, ny, nz;
 };
 
+// The wall-normal metric rows a y-chunk touches (jb .. jb + n - 1 of 1/dy,
+// 1/dyc, wl and wu, zero where a table has no entry), staged in LDS once per
+// block, plus 1/dy of the two wall cells held in registers.  The marching
+// stencils read them from here so that no per-plane global load shares the
+// in-order vector-memory counter with the next plane's prefetch: a wait for
+// such a load would also wait for the prefetch and serialise the pipeline.
+template <typename T>
+struct YTab {
+  const T* s;  // 4 x n values in LDS
+  int n, jb;
+  T rdy_bot, rdy_top;
+  __device__ __forceinline__ T rdy(int j) const { return s[j - jb]; }
+  __device__ __forceinline__ T rdyc(int j) const { return s[n + j - jb]; }
+  __device__ __forceinline__ T wl(int j) const { return s[2 * n + j - jb]; }
+  __device__ __forceinline__ T wu(int j) const { return s[3 * n + j - jb]; }
+};
+
+// Block-cooperative fill of a YTab over rows jb .. jb + n - 1; the caller
+// synchronises before the first read.
+template <typename T>
+__device__ __forceinline__ YTab<T> ytab_fill(T* s, int n, int jb, const Geo<T>& g) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    const int jj = jb + t;
+    const bool in = jj >= 0 && jj < g.ny - 1;
+    s[t] = (jj >= 0 && jj < g.ny) ? g.rdy[jj] : T(0);
+    s[n + t] = in ? g.rdyc[jj] : T(0);
+    s[2 * n + t] = in ? g.wl[jj] : T(0);
+    s[3 * n + t] = in ? g.wu[jj] : T(0);
+  }
+  return YTab<T>{s, n, jb, g.rdy[0], g.rdy[g.ny - 1]};
+}
+
 template <typename T>
 struct RhsOut {
   T ru, rv, rw;
@@ -44,8 +76,8 @@ struct FaceFlux {
 // `below`: the edge products at the lower face (j) when have_below (they are
 // the upper-face products of plane j-1); `above` receives those of face j+1.
 template <typename T, class Acc>
-__device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g, int j, T nu, T fx,
-                                                  bool have_below, FaceFlux<T> below, FaceFlux<T>& above) {
+__device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g, const YTab<T>& Y, int j, T nu,
+                                                  T fx, bool have_below, FaceFlux<T> below, FaceFlux<T>& above) {
   const int ny = g.ny;
   const bool top = (j == ny - 1), bot = (j == 0);
   const T h = T(0.5);
@@ -58,11 +90,11 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g,
   const T uj1 = A.u(1, 0, 0), uj1m = A.u(1, 0, -1), wj1 = A.w(1, 0, 0), wj1m = A.w(1, -1, 0);
   const T vj1 = A.v(1, 0, 0);
   const T ujm = A.u(-1, 0, 0), wjm = A.w(-1, 0, 0), vjm = A.v(-1, 0, 0);
-  const T rdy = g.rdy[j];
+  const T rdy = Y.rdy(j);
   // x-y and y-z edge products at face j+1 (u, w interpolated in y, v in x or z)
   T exy_i = T(0), exy_im = T(0), eyz_k = T(0), eyz_km = T(0);
   if (!top) {
-    const T a = g.wl[j], b = g.wu[j];
+    const T a = Y.wl(j), b = Y.wu(j);
     exy_i = (u0 * a + uj1 * b) * (h * (v0 + vip));
     exy_im = (uim * a + uj1m * b) * (h * (vim + v0));
     eyz_k = (w0 * a + wj1 * b) * (h * (v0 + vkp));
@@ -73,7 +105,7 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g,
     exy_b = below.exy;
     eyz_b = below.eyz;
   } else if (!bot) {
-    const T a = g.wl[j - 1], b = g.wu[j - 1];
+    const T a = Y.wl(j - 1), b = Y.wu(j - 1);
     exy_b = (ujm * a + u0 * b) * (h * (vjm + A.v(-1, 0, 1)));
     eyz_b = (wjm * a + w0 * b) * (h * (vjm + A.v(-1, 1, 0)));
   }
@@ -88,8 +120,8 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g,
   const T nxu = (ucp * ucp - ucm * ucm) * g.rdx + (exy_i - exy_b) * rdy + (exz - exz_km) * g.rdz;
   T lu = (uip - T(2) * u0 + uim) * g.rdx2 + (ukp - T(2) * u0 + ukm) * g.rdz2;
   {
-    const T ft = top ? -T(2) * u0 * g.rdy[ny - 1] : (uj1 - u0) * g.rdyc[j];
-    const T fb = bot ? T(2) * u0 * g.rdy[0] : (u0 - ujm) * g.rdyc[j - 1];
+    const T ft = top ? -T(2) * u0 * Y.rdy_top : (uj1 - u0) * Y.rdyc(j);
+    const T fb = bot ? T(2) * u0 * Y.rdy_bot : (u0 - ujm) * Y.rdyc(j - 1);
     lu += (ft - fb) * rdy;
   }
   // z-momentum
@@ -97,17 +129,17 @@ __device__ __forceinline__ RhsOut<T> momentum_rhs(const Acc& A, const Geo<T>& g,
   const T nzw = (exz - exz_im) * g.rdx + (eyz_k - eyz_b) * rdy + (cwp * cwp - cwm * cwm) * g.rdz;
   T lw = (wip - T(2) * w0 + wim) * g.rdx2 + (wkp - T(2) * w0 + wkm) * g.rdz2;
   {
-    const T ft = top ? -T(2) * w0 * g.rdy[ny - 1] : (wj1 - w0) * g.rdyc[j];
-    const T fb = bot ? T(2) * w0 * g.rdy[0] : (w0 - wjm) * g.rdyc[j - 1];
+    const T ft = top ? -T(2) * w0 * Y.rdy_top : (wj1 - w0) * Y.rdyc(j);
+    const T fb = bot ? T(2) * w0 * Y.rdy_bot : (w0 - wjm) * Y.rdyc(j - 1);
     lw += (ft - fb) * rdy;
   }
   // y-momentum (interior faces only)
   T rv = T(0);
   if (!top) {
     const T ct = h * (vj1 + v0), cb = h * (v0 + vjm);
-    const T nyv = (exy_i - exy_im) * g.rdx + (ct * ct - cb * cb) * g.rdyc[j] + (eyz_k - eyz_km) * g.rdz;
+    const T nyv = (exy_i - exy_im) * g.rdx + (ct * ct - cb * cb) * Y.rdyc(j) + (eyz_k - eyz_km) * g.rdz;
     T lv = (vip - T(2) * v0 + vim) * g.rdx2 + (vkp - T(2) * v0 + vkm) * g.rdz2;
-    lv += ((vj1 - v0) * g.rdy[j + 1] - (v0 - vjm) * rdy) * g.rdyc[j];
+    lv += ((vj1 - v0) * Y.rdy(j + 1) - (v0 - vjm) * rdy) * Y.rdyc(j);
     rv = -nyv + nu * lv;
   }
   RhsOut<T> o;
@@ -151,6 +183,7 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
   using Tl = RkTile<TX, TZ, CY>;
   constexpr int PER = (Tl::PLANE + Tl::THREADS - 1) / Tl::THREADS;  // tile values per thread
   __shared__ T su[3 * Tl::PLANE], sv[3 * Tl::PLANE], sw[3 * Tl::PLANE];
+  __shared__ T sy[4 * (CY + 2)];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
   int b = blockIdx.x;
@@ -209,6 +242,7 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
     c0 = w0[(long)j0 * plane + pid];
   }
   LdsAcc<T, TX, TZ> A{su, sv, sw, 0, 0, 0, (tz + 1) * Tl::SX + tx + 1};
+  const YTab<T> Y = ytab_fill(sy, CY + 2, j0 - 1, g);
   FaceFlux<T> carry{T(0), T(0)};
   bool have = false;
   for (int j = j0; j < j1; ++j) {
@@ -226,7 +260,7 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
     A.sp = ((j + 1) % 3) * Tl::PLANE;
     if (mine) {
       FaceFlux<T> up;
-      const RhsOut<T> r = momentum_rhs<T>(A, g, j, nu, fx, have, carry, up);
+      const RhsOut<T> r = momentum_rhs<T>(A, g, Y, j, nu, fx, have, carry, up);
       carry = up;
       have = true;
       const long id = (long)j * plane + pid;
