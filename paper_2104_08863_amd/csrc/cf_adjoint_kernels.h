@@ -196,27 +196,24 @@ struct AdjPtrs {
   void *gu, *gv, *gw;
 };
 
-// out = s * J_R(state)^T lam (+ A + B when add), lam = c1 A + c2 B (B may be
-// null).  2.5D tiling as in k_rk_stage: a TX x TZ column tile marches over CY
-// planes keeping three planes of the six fields in LDS, the next plane fetched
-// into registers while the current one is computed.
-template <typename T, int TX, int TZ, int CY>
+// out = s * J_R(state)^T lam (+ A + B when ADD), lam = c1 A (+ c2 B when HASB).
+// 2.5D tiling as in k_rk_stage: a TX x TZ column tile marches over CY planes
+// keeping three planes of the six fields in LDS, the raw values of plane j+2
+// fetched into registers while plane j is computed.  lam is formed only when a
+// plane moves from registers to LDS, and every global load is unconditional
+// (clamped address, masked on the move), so the compiler's waits never cover
+// a load still in flight for a later plane.
+template <typename T, int TX, int TZ, int CY, bool HASB, bool ADD>
 __global__ void __launch_bounds__(TX * TZ)
-k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
+k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, TH = TX * TZ;
   constexpr int PER = (PLANE + TH - 1) / TH;
+  constexpr int NF = HASB ? 9 : 6;  // raw fields fetched per tile value
   __shared__ T sm[6 * 3 * PLANE];
   __shared__ T sy[4 * (CY + 2)];
-  const T* u = static_cast<const T*>(P.u);
-  const T* v = static_cast<const T*>(P.v);
-  const T* w = static_cast<const T*>(P.w);
-  const T* au = static_cast<const T*>(P.au);
-  const T* av = static_cast<const T*>(P.av);
-  const T* aw = static_cast<const T*>(P.aw);
-  const T* bu = static_cast<const T*>(P.bu);
-  const T* bv = static_cast<const T*>(P.bv);
-  const T* bw = static_cast<const T*>(P.bw);
-  const bool hasb = (bu != nullptr);
+  const T* src[9] = {static_cast<const T*>(P.u),  static_cast<const T*>(P.v),  static_cast<const T*>(P.w),
+                     static_cast<const T*>(P.au), static_cast<const T*>(P.av), static_cast<const T*>(P.aw),
+                     static_cast<const T*>(P.bu), static_cast<const T*>(P.bv), static_cast<const T*>(P.bw)};
   const Geo<T>& g = G.g;
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
@@ -232,6 +229,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
   const bool mine = (i < nx) && (k < nz);
   const long plane = (long)nx * nz;
   int toff[PER];
+  bool tin[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int idx = threadIdx.x + q * TH;
@@ -240,38 +238,50 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
     if (gi < 0) gi += nx;
     int gk = (k0 + zz - 1) % nz;
     if (gk < 0) gk += nz;
-    toff[q] = (idx < PLANE) ? gk * nx + gi : -1;
+    tin[q] = idx < PLANE;
+    toff[q] = tin[q] ? gk * nx + gi : 0;
   }
-  T r[6][PER];
+  T r[NF][PER];
 #define CF_ADJ_FETCH(jj)                                                        \
-  _Pragma("unroll") for (int q = 0; q < PER; ++q) {                            \
-    _Pragma("unroll") for (int f = 0; f < 6; ++f) r[f][q] = T(0);              \
-    if (toff[q] >= 0 && (jj) >= 0 && (jj) < ny) {                              \
-      const long o = (long)(jj) * plane + toff[q];                             \
-      r[0][q] = u[o];                                                          \
-      r[2][q] = w[o];                                                          \
-      r[3][q] = hasb ? c1 * au[o] + c2 * bu[o] : c1 * au[o];                    \
-      r[5][q] = hasb ? c1 * aw[o] + c2 * bw[o] : c1 * aw[o];                    \
-      if ((jj) < ny - 1) {                                                     \
-        r[1][q] = v[o];                                                        \
-        r[4][q] = hasb ? c1 * av[o] + c2 * bv[o] : c1 * av[o];                  \
+  {                                                                            \
+    const long b_ = (long)min(max((jj), 0), ny - 1) * plane;                   \
+    _Pragma("unroll") for (int q = 0; q < PER; ++q) {                          \
+      _Pragma("unroll") for (int f = 0; f < NF; ++f) r[f][q] = src[f][b_ + toff[q]]; \
+    }                                                                          \
+  }
+#define CF_ADJ_STORE(jj)                                                        \
+  {                                                                            \
+    const int sl_ = (((jj) % 3) + 3) % 3;                                      \
+    const bool pin_ = (jj) >= 0 && (jj) < ny, vin_ = (jj) >= 0 && (jj) < ny - 1; \
+    _Pragma("unroll") for (int q = 0; q < PER; ++q) {                          \
+      if (tin[q]) {                                                            \
+        const int idx = sl_ * PLANE + threadIdx.x + q * TH;                    \
+        _Pragma("unroll") for (int f = 0; f < 3; ++f) {                        \
+          const bool in_ = (f == 1) ? vin_ : pin_;                             \
+          const T lam_ = HASB ? c1 * r[3 + f][q] + c2 * r[(6 + f) % NF][q] : c1 * r[3 + f][q]; \
+          sm[f * 3 * PLANE + idx] = in_ ? r[f][q] : T(0);                      \
+          sm[(3 + f) * 3 * PLANE + idx] = in_ ? lam_ : T(0);                   \
+        }                                                                      \
       }                                                                        \
     }                                                                          \
   }
-#define CF_ADJ_STORE(slot)                                                      \
-  _Pragma("unroll") for (int q = 0; q < PER; ++q) {                            \
-    if (toff[q] >= 0) {                                                        \
-      const int idx = threadIdx.x + q * TH;                                    \
-      _Pragma("unroll") for (int f = 0; f < 6; ++f) sm[(f * 3 + (slot)) * PLANE + idx] = r[f][q]; \
+  const long pid = (long)k * nx + i;
+  const long pidc = (long)min(k, nz - 1) * nx + min(i, nx - 1);
+  T pa[3] = {T(0), T(0), T(0)}, pb[3] = {T(0), T(0), T(0)};
+#define CF_ADJ_LOAD_PT(jj)                                                      \
+  if (ADD) {                                                                   \
+    const long o_ = (long)min((jj), ny - 1) * plane + pidc;                    \
+    _Pragma("unroll") for (int f = 0; f < 3; ++f) {                            \
+      pa[f] = src[3 + f][o_];                                                  \
+      if (HASB) pb[f] = src[(6 + f) % NF][o_];                                 \
     }                                                                          \
   }
   CF_ADJ_FETCH(j0 - 1)
-  CF_ADJ_STORE((j0 + 2) % 3)
+  CF_ADJ_STORE(j0 - 1)
   CF_ADJ_FETCH(j0)
-  CF_ADJ_STORE(j0 % 3)
+  CF_ADJ_STORE(j0)
   CF_ADJ_FETCH(j0 + 1)
   AdjLdsAcc<T, TX, TZ> A{sm, 0, 0, 0, (tz + 1) * SX + tx + 1};
-  const long pid = (long)k * nx + i;
   T* gu = static_cast<T*>(P.gu);
   T* gv = static_cast<T*>(P.gv);
   T* gw = static_cast<T*>(P.gw);
@@ -279,33 +289,34 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s, int add) {
   AdjCarry<T> carry{T(0), T(0), T(0)};
   bool have = false;
   for (int j = j0; j < j1; ++j) {
-    CF_ADJ_STORE((j + 1) % 3)
+    CF_ADJ_STORE(j + 1)
     __syncthreads();
+    CF_ADJ_LOAD_PT(j)
     CF_ADJ_FETCH(j + 2)
     A.sm = ((j + 2) % 3) * PLANE;
     A.s0 = (j % 3) * PLANE;
     A.sp = ((j + 1) % 3) * PLANE;
+    AdjCarry<T> up;
+    const AdjOut<T> o = rhs_adjoint_point<T>(A, G, Y, j, nu, have, carry, up);
+    carry = up;
+    have = true;
+    T ou = s * o.gu, ov = s * o.gv, ow = s * o.gw;
+    if (ADD) {
+      ou += HASB ? pa[0] + pb[0] : pa[0];
+      ov += HASB ? pa[1] + pb[1] : pa[1];
+      ow += HASB ? pa[2] + pb[2] : pa[2];
+    }
     if (mine) {
-      AdjCarry<T> up;
-      const AdjOut<T> o = rhs_adjoint_point<T>(A, G, Y, j, nu, have, carry, up);
-      carry = up;
-      have = true;
       const long id = (long)j * plane + pid;
-      const bool top = (j == ny - 1);
-      T ou = s * o.gu, ov = s * o.gv, ow = s * o.gw;
-      if (add) {
-        ou += au[id] + (hasb ? bu[id] : T(0));
-        ow += aw[id] + (hasb ? bw[id] : T(0));
-        ov += top ? T(0) : av[id] + (hasb ? bv[id] : T(0));
-      }
       gu[id] = ou;
-      gv[id] = top ? T(0) : ov;
+      gv[id] = (j == ny - 1) ? T(0) : ov;
       gw[id] = ow;
     }
     __syncthreads();
   }
 #undef CF_ADJ_FETCH
 #undef CF_ADJ_STORE
+#undef CF_ADJ_LOAD_PT
 }
 
 // g* = g - W G phi (weighted correction of the projection transpose);

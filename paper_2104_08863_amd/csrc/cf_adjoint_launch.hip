@@ -14,8 +14,15 @@ hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, c
   AdjPtrs P{u, v, w, au, av, aw, bu, bv, bw, gu, gv, gw};
   const long blocks = (long)((g.g.nx + ADJ_TX - 1) / ADJ_TX) * ((g.g.nz + ADJ_TZ - 1) / ADJ_TZ) *
                       ((g.g.ny + ADJ_CY - 1) / ADJ_CY);
-  hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY>), dim3(blocks), dim3(ADJ_TX * ADJ_TZ), 0, st, P, c1,
-                     c2, g, nu, s, add);
+  const dim3 grid(blocks), block(ADJ_TX * ADJ_TZ);
+  if (bu != nullptr && add)
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, true, true>), grid, block, 0, st, P, c1, c2, g, nu, s);
+  else if (bu != nullptr)
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, true, false>), grid, block, 0, st, P, c1, c2, g, nu, s);
+  else if (add)
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, false, true>), grid, block, 0, st, P, c1, c2, g, nu, s);
+  else
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, false, false>), grid, block, 0, st, P, c1, c2, g, nu, s);
   return hipGetLastError();
 }
 
