@@ -30,7 +30,6 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # a plain elementwise kernel reading and writing a known size gives on this
 # chip).  Keyed by (kernel, workload); drop an entry when its kernel changes.
 MEASURED_TRAFFIC = {
-    ("rk_stage2", "step550"): (4189164.2 * 2.0 + 3145728.0 * 1.0) * 1024,
 }
 
 
