@@ -193,7 +193,8 @@ enum {
   CF_K_CORRECT = 9,   /* pressure-gradient correction u1 = u* - dt G p */
   CF_K_ADJ_RHS = 10,  /* transposed momentum right-hand side */
   CF_K_ADJ_CORRECT = 11, /* weighted correction of the transposed projection */
-  CF_K_COUNT = 12
+  CF_K_RK_FUSED = 12, /* both RK2 stages in one marching pass (forward step) */
+  CF_K_COUNT = 13
 };
 cf_status cf_plan_set_timing(cf_plan* plan, int enable);
 cf_status cf_plan_reset_timing(cf_plan* plan);

@@ -17,7 +17,7 @@ HOSTLIB_PATH = os.path.join(PKG, "libchanflow_host.so")
 CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMERIC = range(6)
 CF_FP64, CF_MIXED = 0, 1
 KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
-           "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted"]
+           "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted", "rk2_fused"]
 CF_PLAN_STEP, CF_PLAN_ADJOINT = 1, 2
 
 

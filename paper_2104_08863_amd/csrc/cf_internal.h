@@ -101,6 +101,10 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
                            hipStream_t s);
 
 // u1 = us - dt G p in place.
+// Both RK2 stages in one pass: uo = (u + ub)/2 + dt/2 R(ub), ub = u + dt R(u).
+template <typename T>
+hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu,
+                            T fx, hipStream_t s);
 template <typename T>
 hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s);
 

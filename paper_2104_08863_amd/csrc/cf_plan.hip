@@ -438,20 +438,42 @@ cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
   return CF_OK;
 }
 
+// The RK2 momentum update u1 = (u + ub)/2 + dt/2 R(ub), ub = u + dt R(u).  One
+// fused pass when the outputs are separate arrays; when an output overlaps an
+// input (in-place step) the fused pass would read cells other blocks already
+// overwrote, so the two stages run as separate passes through the stage-1
+// workspace (stage 2 reads the old field only at the cell it writes).
+template <typename T>
+cf_status rk2_t(cf_plan* pl, const T* u, const T* v, const T* w, T* u1, T* v1, T* w1, const cf::Geo<T>& g, T dt,
+                T nu, T fx, hipStream_t s) {
+  const uintptr_t bytes = (uintptr_t)pl->nx * pl->ny * pl->nz * sizeof(T);
+  const T* in[3] = {u, v, w};
+  const T* out[3] = {u1, v1, w1};
+  bool overlap = false;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const uintptr_t x = reinterpret_cast<uintptr_t>(in[a]), y = reinterpret_cast<uintptr_t>(out[b]);
+      overlap = overlap || (x < y + bytes && y < x + bytes);
+    }
+  if (!overlap)
+    return timed(pl, CF_K_RK_FUSED, s, "fused rk2",
+                 [&] { return cf::launch_rk2_fused<T>(u, v, w, u1, v1, w1, g, dt, nu, fx, s); });
+  T* ub = static_cast<T*>(pl->ub);
+  T* vb = static_cast<T*>(pl->vb);
+  T* wb = static_cast<T*>(pl->wb);
+  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
+    return cf::launch_rk_stage<T>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, g, dt, nu, fx, s);
+  }));
+  return timed(pl, CF_K_RK2, s, "rk stage 2",
+               [&] { return cf::launch_rk_stage<T>(2, ub, vb, wb, u, v, w, u1, v1, w1, g, dt, nu, fx, s); });
+}
+
 // One mixed-precision projection step (FP32 velocity state, FP64 pressure).
 cf_status step_mixed(cf_plan* pl, const float* u, const float* v, const float* w, float* u1, float* v1,
                      float* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
-  float* ub = static_cast<float*>(pl->ub);
-  float* vb = static_cast<float*>(pl->vb);
-  float* wb = static_cast<float*>(pl->wb);
   double* pp = p ? p : pl->pws;
   const float fdt = float(dt), fnu = float(nu), ffx = float(fx);
-  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
-    return cf::launch_rk_stage<float>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g32, fdt, fnu, ffx, s);
-  }));
-  CF_TRY(timed(pl, CF_K_RK2, s, "rk stage 2", [&] {
-    return cf::launch_rk_stage<float>(2, ub, vb, wb, u, v, w, u1, v1, w1, pl->g32, fdt, fnu, ffx, s);
-  }));
+  CF_TRY(rk2_t<float>(pl, u, v, w, u1, v1, w1, pl->g32, fdt, fnu, ffx, s));
   CF_TRY(poisson_mixed(pl, MixedRhs{1, nullptr, u1, v1, w1, 1.0 / dt}, pp, s));
   CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
     return cf::launch_correct<float>(u1, v1, w1, pp, pl->g32, fdt, s);
@@ -462,16 +484,8 @@ cf_status step_mixed(cf_plan* pl, const float* u, const float* v, const float* w
 // One FP64 projection step.
 cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w, double* u1, double* v1,
                  double* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
-  double* ub = static_cast<double*>(pl->ub);
-  double* vb = static_cast<double*>(pl->vb);
-  double* wb = static_cast<double*>(pl->wb);
   double* pp = p ? p : pl->pws;
-  CF_TRY(timed(pl, CF_K_RK1, s, "rk stage 1", [&] {
-    return cf::launch_rk_stage<double>(1, u, v, w, nullptr, nullptr, nullptr, ub, vb, wb, pl->g64, dt, nu, fx, s);
-  }));
-  CF_TRY(timed(pl, CF_K_RK2, s, "rk stage 2", [&] {
-    return cf::launch_rk_stage<double>(2, ub, vb, wb, u, v, w, u1, v1, w1, pl->g64, dt, nu, fx, s);
-  }));
+  CF_TRY(rk2_t<double>(pl, u, v, w, u1, v1, w1, pl->g64, dt, nu, fx, s));
   cx<double>* B = static_cast<cx<double>*>(pl->specB);
   CF_TRY(forward_div_t<double>(pl, u1, v1, w1, 1.0 / dt, B, s));
   CF_TRY(solve_t<double>(pl, B, B, s));
@@ -1007,7 +1021,8 @@ cf_status cf_plan_get_timing(cf_plan* pl, int kernel, double* total_ms, long lon
 const char* cf_kernel_name(int k) {
   static const char* names[CF_K_COUNT] = {"r2c_x",     "fft_z_fwd", "ysolve",      "special_lines",
                                           "fft_z_inv", "c2r_x",     "divergence",  "rk_stage1",
-                                          "rk_stage2", "correct",   "rhs_adjoint", "correct_weighted"};
+                                          "rk_stage2", "correct",   "rhs_adjoint", "correct_weighted",
+                                          "rk2_fused"};
   return (k >= 0 && k < CF_K_COUNT) ? names[k] : "unknown";
 }
 

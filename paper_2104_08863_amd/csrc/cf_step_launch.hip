@@ -1,5 +1,6 @@
 // Launch of the RK2 momentum stages and the pressure-gradient correction.
 #include "cf_internal.h"
+#include "cf_rk_fused.h"
 #include "cf_step_kernels.h"
 
 namespace cf {
@@ -23,6 +24,20 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
   return hipGetLastError();
 }
 
+// Fused RK2 tile: 64 x 8 columns (stage 1 on the 66 x 10 grown tile), chunks of
+// 32 planes.
+constexpr int RKF_TX = 64, RKF_TZ = 8, RKF_CY = 32;
+
+template <typename T>
+hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu,
+                            T fx, hipStream_t s) {
+  const long blocks = (long)((g.nx + RKF_TX - 1) / RKF_TX) * ((g.nz + RKF_TZ - 1) / RKF_TZ) *
+                      ((g.ny + RKF_CY - 1) / RKF_CY);
+  hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, RKF_CY>), dim3(blocks), dim3(RKF_TX * RKF_TZ), 0, s, u, v, w,
+                     uo, vo, wo, g, dt, nu, fx);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s) {
   const long n = (long)g.nx * g.ny * g.nz;
@@ -35,6 +50,8 @@ hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T 
 #define CF_INST(T)                                                                                     \
   template hipError_t launch_rk_stage<T>(int, const T*, const T*, const T*, const T*, const T*,        \
                                          const T*, T*, T*, T*, const Geo<T>&, T, T, T, hipStream_t); \
+  template hipError_t launch_rk2_fused<T>(const T*, const T*, const T*, T*, T*, T*, const Geo<T>&, T, T, T, \
+                                          hipStream_t);                                                   \
   template hipError_t launch_correct<T>(T*, T*, T*, const double*, const Geo<T>&, T, hipStream_t);
 CF_INST(double)
 CF_INST(float)
