@@ -50,6 +50,7 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_ph
         "special_lines": 0.0,
         "rk_stage1": 6 * phys,
         "rk_stage2": 9 * phys,
+        "rk2_fused": 6 * phys,
         "correct": 6 * phys + nx * ny * nz * 8,
     }[name]
 

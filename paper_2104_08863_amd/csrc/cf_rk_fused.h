@@ -9,9 +9,12 @@
 // in the split stages.
 //
 // Both stages use the edge products carried up from the plane below and the
-// plane-below values of the thread's own column from registers, so each LDS
-// ring keeps two planes (j, j+1) only.  The first plane of a chunk gets those
-// carries from a short prologue over the two planes below it.
+// plane-below values of the thread's own column from registers, so the input
+// ring keeps two planes (j, j+1).  Stage 2 runs two planes behind stage 1 (the
+// ub ring keeps three planes), so within one barrier interval the two stages
+// are independent and their LDS reads and arithmetic interleave.  The first
+// planes of a chunk get the carries from a short prologue over the two planes
+// below it.
 #pragma once
 
 #include "cf_step_kernels.h"
@@ -97,19 +100,28 @@ struct RkFusedTile {
   static constexpr int PER = (UPL + TH - 1) / TH;                // input values per thread per plane
 };
 
+// At least four waves per SIMD: the register cap this sets (128 VGPRs, some
+// spilled in FP64) costs less than the latency hiding fewer waves would lose.
+// Blocks are dealt round-robin to the 8 XCDs; the tile index is remapped so
+// that each XCD walks a contiguous run of tiles and neighbouring tiles share
+// the halo lines in one L2.
 template <typename T, int TX, int TZ, int CY>
-__global__ void __launch_bounds__(TX * TZ)
+__global__ void __launch_bounds__(TX * TZ, 4)
 k_rk2_fused(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, T* uo, T* vo, T* wo,
             Geo<T> g, T dt, T nu, T fx) {
   using Tl = RkFusedTile<TX, TZ>;
   constexpr int TH = Tl::TH, EX = Tl::EX, EPL = Tl::EPL, UX = Tl::UX, UPL = Tl::UPL, PER = Tl::PER;
   static_assert(Tl::NRING <= TH, "the grown tile's outer cells must fit one pass of the block");
   __shared__ T su[2 * UPL], sv[2 * UPL], sw[2 * UPL];
-  __shared__ T bu[2 * EPL], bv[2 * EPL], bw[2 * EPL];
+  __shared__ T bu[3 * EPL], bv[3 * EPL], bw[3 * EPL];
   __shared__ T sy[4 * (CY + 4)];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
   int b = blockIdx.x;
+  {
+    const int nb = gridDim.x;
+    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
+  }
   const int bx = b % ntx;
   b /= ntx;
   const int bz = b % ntz;
@@ -169,7 +181,7 @@ k_rk2_fused(const T* __restrict__ u, const T* __restrict__ v, const T* __restric
   }
   const int ubB = (ezB + 1) * UX + exB + 1, eB = ezB * EX + exB;
 #define CF_US(jj) (((jj) & 1) * UPL)
-#define CF_BS(jj) (((jj) & 1) * EPL)
+#define CF_BS(jj) ((((jj) + 3) % 3) * EPL)
 
   CF_RKF_FETCH(j0 - 2)
   CF_RKF_STORE(j0 - 2)
@@ -221,31 +233,42 @@ k_rk2_fused(const T* __restrict__ u, const T* __restrict__ v, const T* __restric
     s2.wm = A.w(0, 0, 0);
   }
   const T hh = T(0.5), hd = T(0.5) * dt;
-  for (int s = j0; s < j1; ++s) {
+  // iteration s: stage 1 at plane s+1 and stage 2 at plane s-1, independent of
+  // each other within the barrier interval (three ub planes in LDS)
+  T p0u = T(0), p0v = T(0), p0w = T(0);
+  for (int s = j0; s <= j1; ++s) {
     CF_RKF_STORE(s + 2)
     __syncthreads();
     CF_RKF_FETCH(s + 3)
-    const T f0u = sA.um, f0v = sA.vm, f0w = sA.wm;  // u, v, w of this cell at plane s
-    rk_stage1_point<T, UX>(su, sv, sw, bu, bv, bw, CF_US(s + 1), CF_US(s + 2), ubA, CF_BS(s + 1) + eA, sA, g, Y,
-                           s + 1, dt, nu, fx);
-    if (hasB)
-      rk_stage1_point<T, UX>(su, sv, sw, bu, bv, bw, CF_US(s + 1), CF_US(s + 2), ubB, CF_BS(s + 1) + eB, sB, g, Y,
+    const T c0u = sA.um, c0v = sA.vm, c0w = sA.wm;  // u, v, w of this cell at plane s
+    if (s + 1 <= j1) {
+      rk_stage1_point<T, UX>(su, sv, sw, bu, bv, bw, CF_US(s + 1), CF_US(s + 2), ubA, CF_BS(s + 1) + eA, sA, g, Y,
                              s + 1, dt, nu, fx);
-    __syncthreads();
-    const Ring2Acc<T, EX> B{bu, bv, bw, CF_BS(s), CF_BS(s + 1), eA, s2.um, s2.vm, s2.wm};
-    const T uc = B.u(0, 0, 0), vc = B.v(0, 0, 0), wc = B.w(0, 0, 0);
-    FaceFlux<T> up;
-    const RhsOut<T> r = momentum_rhs<T>(B, g, Y, s, nu, fx, true, s2.c, up);
-    s2.c = up;
-    s2.um = uc;
-    s2.vm = vc;
-    s2.wm = wc;
-    if (mine) {
-      const long id = (long)s * plane + (long)k * nx + i;
-      uo[id] = hh * (f0u + uc) + hd * r.ru;
-      vo[id] = (s == ny - 1) ? T(0) : hh * (f0v + vc) + hd * r.rv;
-      wo[id] = hh * (f0w + wc) + hd * r.rw;
+      if (hasB)
+        rk_stage1_point<T, UX>(su, sv, sw, bu, bv, bw, CF_US(s + 1), CF_US(s + 2), ubB, CF_BS(s + 1) + eB, sB, g,
+                               Y, s + 1, dt, nu, fx);
     }
+    if (s > j0) {
+      const int q = s - 1;
+      const Ring2Acc<T, EX> B{bu, bv, bw, CF_BS(q), CF_BS(q + 1), eA, s2.um, s2.vm, s2.wm};
+      const T uc = B.u(0, 0, 0), vc = B.v(0, 0, 0), wc = B.w(0, 0, 0);
+      FaceFlux<T> up;
+      const RhsOut<T> r = momentum_rhs<T>(B, g, Y, q, nu, fx, true, s2.c, up);
+      s2.c = up;
+      s2.um = uc;
+      s2.vm = vc;
+      s2.wm = wc;
+      if (mine) {
+        const long id = (long)q * plane + (long)k * nx + i;
+        uo[id] = hh * (p0u + uc) + hd * r.ru;
+        vo[id] = (q == ny - 1) ? T(0) : hh * (p0v + vc) + hd * r.rv;
+        wo[id] = hh * (p0w + wc) + hd * r.rw;
+      }
+    }
+    p0u = c0u;
+    p0v = c0v;
+    p0w = c0w;
+    __syncthreads();
   }
 #undef CF_RKF_FETCH
 #undef CF_RKF_STORE

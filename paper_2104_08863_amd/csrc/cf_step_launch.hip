@@ -24,9 +24,10 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
   return hipGetLastError();
 }
 
-// Fused RK2 tile: 64 x 8 columns (stage 1 on the 66 x 10 grown tile), chunks of
-// 32 planes.
-constexpr int RKF_TX = 64, RKF_TZ = 8, RKF_CY = 32;
+// Fused RK2 tile: 64 x 16 columns, one block of 16 waves per CU (stage 1 on the
+// 66 x 18 grown tile, whose 164 outer cells keep 3 of the 16 waves busy for one
+// more stencil pass), chunks of 128 planes.
+constexpr int RKF_TX = 64, RKF_TZ = 16, RKF_CY = 128;
 
 template <typename T>
 hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu,

@@ -16,8 +16,9 @@ CASES = [
     (64, 64, 64, 2.0, 1e-3, 1 / 550),
     (16, 8, 6, 1.0, 1e-2, 1 / 50),
     (128, 32, 96, 2.5, 2e-4, 1 / 550),
-    # partial x and z tiles and three y-chunks with a ragged last one
+    # partial x and z tiles of the RK kernels and y-chunks with a ragged last one
     (96, 70, 12, 2.0, 1e-3, 1 / 550),
+    (96, 136, 24, 2.5, 1e-3, 1 / 550),
 ]
 
 
