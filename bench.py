@@ -33,6 +33,53 @@ MEASURED_TRAFFIC = {
 }
 
 
+def _pmc_load(base, name):
+    import collections
+    import csv
+    import re
+    rows = list(csv.DictReader(open(f"{base}/{name}/run_counter_collection.csv")))
+    agg = collections.defaultdict(list)
+    for r in rows:
+        k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+        agg[(k, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in agg.items()}
+
+
+def summarize_pmc(base):
+    """Markdown table of rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
+    averaged over dispatches) from the passes copy_fetch/, copy_write/ (the
+    --calibrate-copy run: one elementwise kernel reading and writing 1 GiB) and
+    fetch/, write/ (the bench run) under `base`, each scaled by the factor the
+    calibration kernel gives for the same counter."""
+    cf, cw = _pmc_load(base, "copy_fetch"), _pmc_load(base, "copy_write")
+    copy = [k for (k, c) in cf if "CUDAFunctor" in k][0]
+    kib = 1024 * 1024
+    f_fac, w_fac = kib / cf[(copy, "FETCH_SIZE")], kib / cw[(copy, "WRITE_SIZE")]
+    fe, wr = _pmc_load(base, "fetch"), _pmc_load(base, "write")
+    out = [f"calibration (elementwise kernel reading and writing 1 GiB): FETCH_SIZE "
+           f"{cf[(copy, 'FETCH_SIZE')]:.0f} KiB -> factor {f_fac:.3f}; WRITE_SIZE "
+           f"{cw[(copy, 'WRITE_SIZE')]:.0f} KiB -> factor {w_fac:.3f}", "",
+           "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB (scaled) | write GB (scaled) |",
+           "|---|---:|---:|---:|---:|"]
+    names = sorted({k for (k, c) in fe if k.startswith("cf::")}, key=lambda k: -fe[(k, "FETCH_SIZE")])
+    for k in names:
+        f, w = fe[(k, "FETCH_SIZE")], wr.get((k, "WRITE_SIZE"), float("nan"))
+        out.append(f"| `{k}` | {f:.0f} | {w:.0f} | {f * f_fac * 1024 / 1e9:.3f} | {w * w_fac * 1024 / 1e9:.3f} |")
+    return "\n".join(out)
+
+
+def summarize_trace(path):
+    """Markdown table of a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+    import re
+    out = ["| kernel | calls | avg us | min us | max us | % |", "|---|---:|---:|---:|---:|---:|"]
+    for r in csv.DictReader(open(path)):
+        n = re.sub(r"\(.*", "", r["Name"]).replace("void ", "")
+        out.append(f"| `{n}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                   f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out)
+
+
 def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_phys: int = 8,
                  fused_div: bool = False) -> float:
     """Algorithmic bytes of one launch of a kernel class: every array the
@@ -206,10 +253,18 @@ def main():
                     help="timed calls per secondary figure (Poisson FP64/mixed, fwd+adjoint); 0 skips them")
     ap.add_argument("--poisson-only", action="store_true",
                     help="time the Poisson solve alone instead of the projection step")
+    ap.add_argument("--summarize-pmc", metavar="DIR", help="print the traffic table of rocprofv3 --pmc passes and exit")
+    ap.add_argument("--summarize-trace", metavar="CSV", help="print a rocprofv3 kernel_stats.csv as markdown and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain elementwise kernel reading and writing BYTES bytes "
                          "three times (reference for hardware traffic counters) and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace))
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy // 8

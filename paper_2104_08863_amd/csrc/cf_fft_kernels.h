@@ -30,6 +30,13 @@ struct FftT {
   static constexpr int RL = P.r[P.np - 1];
 };
 
+// LDS position of element e of a line: one pad slot after every 16 elements.
+// The exchange after a first radix-16 pass writes element b*16 + r from thread
+// b, a stride of 16 elements that would put every lane of a quarter-wave on
+// the same LDS banks; the pad turns it into a stride of 17.
+CF_HD constexpr int lpad(int e) { return e + (e >> 4); }
+constexpr int lpad_len(int n) { return n + (n >> 4); }
+
 // Runs passes PASS..np-1 on the registers x (pass PASS input order on entry,
 // last-pass output order on exit).  sl: this line's LDS (N slots).  Every
 // thread of the block must call this (it contains block barriers).
@@ -48,14 +55,14 @@ __device__ __forceinline__ void fft_passes(cx<T>* x, int t, cx<T>* sl, const cx<
     for (int q = 0; q < E / RP; ++q) {
       const int b = t + q * TPL;
 #pragma unroll
-      for (int r = 0; r < RP; ++r) sl[st_out(RP, NSP, b, r)] = x[q * RP + r];
+      for (int r = 0; r < RP; ++r) sl[lpad(st_out(RP, NSP, b, r))] = x[q * RP + r];
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < E / R; ++q) {
       const int b = t + q * TPL;
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[q * R + r] = sl[st_in(N, R, b, r)];
+      for (int r = 0; r < R; ++r) x[q * R + r] = sl[lpad(st_in(N, R, b, r))];
     }
   }
 #pragma unroll
@@ -73,7 +80,7 @@ constexpr int lds_lines(int n, int tpl, int esize, int budget) {
 // ---------------------------------------------------------------- z (contiguous lines)
 template <typename T, int N>
 struct ZCfg {
-  static constexpr int LPB = lds_lines(N, FftT<N>::TPL, int(sizeof(cx<T>)), 32768);
+  static constexpr int LPB = lds_lines(lpad_len(N), FftT<N>::TPL, int(sizeof(cx<T>)), 32768);
   static constexpr int THREADS = LPB * FftT<N>::TPL;
 };
 
@@ -83,7 +90,7 @@ k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __r
         int ni) {
   using F = FftT<N>;
   constexpr int LPB = ZCfg<T, N>::LPB;
-  __shared__ cx<T> lds[LPB * N];
+  __shared__ cx<T> lds[LPB * lpad_len(N)];
   const int tl = threadIdx.x % F::TPL;
   const int lb = threadIdx.x / F::TPL;
   const long nlines = (long)no * ni;
@@ -99,7 +106,7 @@ k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __r
 #pragma unroll
     for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? g[st_in(N, F::R0, b, r)] : mk(T(0), T(0));
   }
-  fft_passes<N, INV, T, 0>(x, tl, lds + lb * N, tw);
+  fft_passes<N, INV, T, 0>(x, tl, lds + lb * lpad_len(N), tw);
   if (ok) {
 #pragma unroll
     for (int q = 0; q < F::E / F::RL; ++q) {
@@ -115,7 +122,7 @@ template <typename T, int NH>
 struct XCfg {
   // rows per block: aim for 128-byte runs of kz in the transposed spectrum
   static constexpr int KWANT = int(128 / sizeof(cx<T>));
-  static constexpr int S = NH + 1;  // padded LDS row stride (also holds kx = NH)
+  static constexpr int S = lpad(NH) + 1;  // LDS row stride (holds kx = 0..NH at lpad(kx))
   static constexpr int kfit(int k) {
     return (k > 1 && (k * S * int(sizeof(cx<T>)) > 73728 || k * FftT<NH>::TPL > 1024)) ? kfit(k / 2) : k;
   }
@@ -288,7 +295,7 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const c
   for (int q = 0; q < F::E / F::RL; ++q) {
     const int b = tl + q * F::TPL;
 #pragma unroll
-    for (int r = 0; r < F::RL; ++r) sl[b + r * (NH / F::RL)] = x[q * F::RL + r];
+    for (int r = 0; r < F::RL; ++r) sl[lpad(b + r * (NH / F::RL))] = x[q * F::RL + r];
   }
   __syncthreads();
   const long plane = (long)j * NKX;
@@ -301,7 +308,7 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const c
     const int kx = idx / K;
     if (idx < ITEMS && k0 + r < nz) {
       const cx<T>* row = lds + r * S;
-      cx<T> X = r2c_post(row[kx == NH ? 0 : kx], row[kx == 0 ? 0 : NH - kx], twp[kx]);
+      cx<T> X = r2c_post(row[lpad(kx == NH ? 0 : kx)], row[lpad(kx == 0 ? 0 : NH - kx)], twp[kx]);
       spec[(plane + kx) * nz + k0 + r] = X;
     }
   }
@@ -361,7 +368,7 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* __restrict__ tw,
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int idx = threadIdx.x + it * TH;
-      if (idx < ITEMS) lds[(idx % K) * S + idx / K] = v[it];
+      if (idx < ITEMS) lds[(idx % K) * S + lpad(idx / K)] = v[it];
     }
   }
   __syncthreads();
@@ -376,7 +383,7 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* __restrict__ tw,
 #pragma unroll
     for (int r = 0; r < F::R0; ++r) {
       const int m = st_in(NH, F::R0, b, r);
-      cx<T> a = sl[m], bb = sl[NH - m];
+      cx<T> a = sl[lpad(m)], bb = sl[lpad(NH - m)];
       if (m == 0) {
         a.im = T(0);
         bb.im = T(0);
