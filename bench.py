@@ -30,6 +30,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # a plain elementwise kernel reading and writing a known size gives on this
 # chip).  Keyed by (kernel, workload); drop an entry when its kernel changes.
 MEASURED_TRAFFIC = {
+    # k_rk2_fused<double, 64, 16, 128>: FETCH_SIZE 1812216 KiB, WRITE_SIZE 3378268 KiB
+    ("rk2_fused", "step550"): (1812216.2 * 2.0 + 3378268.3 * 1.0) * 1024,
 }
 
 
