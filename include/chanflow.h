@@ -138,6 +138,17 @@ cf_status cf_projection_step(cf_plan* plan, const void* u, const void* v, const 
                              void* stream);
 
 /*
+ * The RK2 predictor of cf_projection_step alone (test hook; Section 2, Eq. (5)-(6)):
+ *   ub = u + dt R(u),  u* = (u + ub)/2 + dt/2 R(ub),
+ * written to (us, vs, ws); the top-wall v plane of the output is 0.  Arrays and
+ * precision as in cf_projection_step; outputs that do not overlap the inputs take
+ * the fused single-pass kernel, overlapping ones the two split stages.  The plan
+ * must have been created with CF_PLAN_STEP.
+ */
+cf_status cf_rk2_predictor(cf_plan* plan, const void* u, const void* v, const void* w, void* us, void* vs,
+                           void* ws, double dt, double nu, double fx, void* stream);
+
+/*
  * Adjoint of cf_projection_step (the differentiated form of Section 2, Eq. (3)-(7)):
  * given the step input (u, v, w) and g1 = dJ/d(u1, v1, w1), returns
  * g = dJ/d(u, v, w) (Euclidean gradient, what autograd expects), with

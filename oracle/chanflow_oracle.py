@@ -301,8 +301,9 @@ def momentum_rhs(u, v, w, box: Box, nu: float, fx: float):
 # ----------------------------------------------------------------------------
 # One projection step (Eq. (4)-(7), RK2 of Eq. (5)-(6), one pressure solve)
 # ----------------------------------------------------------------------------
-def projection_step(u, v, w, box: Box, dt: float, nu: float, fx: float,
-                    return_pressure: bool = False):
+def rk2_predictor(u, v, w, box: Box, dt: float, nu: float, fx: float):
+    """Heun predictor of Eq. (5)-(6): ub = u + dt R(u),
+    u* = u + dt/2 (R(u) + R(ub)); v is zero on the top wall."""
     v = _wall_v(v)
     r0 = momentum_rhs(u, v, w, box, nu, fx)
     ub = u + dt * r0[0]
@@ -312,6 +313,12 @@ def projection_step(u, v, w, box: Box, dt: float, nu: float, fx: float,
     us = u + 0.5 * dt * (r0[0] + r1[0])
     vs = _wall_v(v + 0.5 * dt * (r0[1] + r1[1]))
     ws = w + 0.5 * dt * (r0[2] + r1[2])
+    return us, vs, ws
+
+
+def projection_step(u, v, w, box: Box, dt: float, nu: float, fx: float,
+                    return_pressure: bool = False):
+    us, vs, ws = rk2_predictor(u, v, w, box, dt, nu, fx)
     p = poisson(divergence(us, vs, ws, box) / dt, box)
     gu, gv, gw = gradient(p, box)
     out = (us - dt * gu, vs - dt * gv, ws - dt * gw)
@@ -453,7 +460,7 @@ __all__ = [
     "Box", "y_coefficients", "modified_wavenumbers", "mean_w", "forward_transform",
     "inverse_transform", "thomas", "solve_spectral", "solve_mean_line", "poisson",
     "divergence", "gradient", "laplacian_p", "advection", "laplacian_vel",
-    "momentum_rhs", "projection_step", "rollout", "rollout_loss_and_grad",
+    "momentum_rhs", "rk2_predictor", "projection_step", "rollout", "rollout_loss_and_grad",
     "pdd_solve", "pdd_indicator", "line_coefficients", "set_threads",
 ]
 

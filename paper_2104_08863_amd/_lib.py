@@ -47,6 +47,7 @@ SIGNATURES = {
     "cf_poisson_solve": (_I, [_P, _P, _P, _P]),
     "cf_divergence": (_I, [_P, _P, _P, _P, _P, _D, _P]),
     "cf_projection_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
+    "cf_rk2_predictor": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
     "cf_projection_step_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
     "cf_rhs_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _P]),
     "cf_forward_spectral": (_I, [_P, _P, _P, _P]),

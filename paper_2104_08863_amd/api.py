@@ -154,6 +154,21 @@ class Plan:
                 "cf_projection_step")
         return out
 
+    def rk2_predictor(self, u, v, w, dt: float, nu: float, fx: float, out=None):
+        """The RK2 predictor u* of a projection step alone (test hook); returns
+        (us, vs, ws).  out may be (u, v, w) themselves."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w")):
+            self._field(t, n, sd)
+        if out is None:
+            out = (self._new(sd), self._new(sd), self._new(sd))
+        for t, n in zip(out, ("us", "vs", "ws")):
+            self._field(t, n, sd)
+        L.check(L.lib().cf_rk2_predictor(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out[0]), _ptr(out[1]),
+                                         _ptr(out[2]), float(dt), float(nu), float(fx), _stream()),
+                "cf_rk2_predictor")
+        return out
+
     def projection_step_adjoint(self, u, v, w, gu1, gv1, gw1, dt: float, nu: float, fx: float, out=None):
         """dJ/d(u, v, w) of one projection step from dJ/d(u1, v1, w1)."""
         sd = self.state_dtype

@@ -940,6 +940,25 @@ cf_status cf_projection_step(cf_plan* pl, const void* u, const void* v, const vo
                 static_cast<double*>(u1), static_cast<double*>(v1), static_cast<double*>(w1), p, dt, nu, fx, s);
 }
 
+cf_status cf_rk2_predictor(cf_plan* pl, const void* u, const void* v, const void* w, void* us, void* vs, void* ws,
+                           double dt, double nu, double fx, void* stream) {
+  CF_TRY(check_plan(pl));
+  if (!(pl->opt.flags & CF_PLAN_STEP)) return fail(CF_ERR_ARG, "plan was created without CF_PLAN_STEP");
+  const void* ptrs[6] = {u, v, w, us, vs, ws};
+  const char* names[6] = {"u", "v", "w", "us", "vs", "ws"};
+  for (int q = 0; q < 6; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
+  if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed())
+    return rk2_t<float>(pl, static_cast<const float*>(u), static_cast<const float*>(v), static_cast<const float*>(w),
+                        static_cast<float*>(us), static_cast<float*>(vs), static_cast<float*>(ws), pl->g32, float(dt),
+                        float(nu), float(fx), s);
+  return rk2_t<double>(pl, static_cast<const double*>(u), static_cast<const double*>(v),
+                       static_cast<const double*>(w), static_cast<double*>(us), static_cast<double*>(vs),
+                       static_cast<double*>(ws), pl->g64, dt, nu, fx, s);
+}
+
 cf_status cf_projection_step_adjoint(cf_plan* pl, const void* u, const void* v, const void* w,
                                      const void* gu1, const void* gv1, const void* gw1, void* gu, void* gv,
                                      void* gw, double dt, double nu, double fx, void* stream) {

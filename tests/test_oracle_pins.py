@@ -342,3 +342,34 @@ def test_oracle_gradient_matches_finite_differences():
         fd = (J(u + h * du, v + h * dv, w + h * dw) - J(u - h * du, v - h * dv, w - h * dw)) / (2 * h)
         an = ((gu * du).sum() + (gv * dv).sum() + (gw * dw).sum()).item()
         assert abs(fd - an) <= 1e-7 * max(abs(fd), abs(an))
+
+
+def test_rk2_predictor_reaches_two_cells_in_x_and_z():
+    """Locality of the Heun predictor (two stencil applications of reach one):
+    the oracle on a periodic 9x9-column window reproduces the window's centre
+    column of the full-grid result exactly.  The full-size GPU parity test of
+    the predictor relies on this."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2104_08863_amd import synth
+    nx, ny, nz = 32, 16, 24
+    yf = synth.tanh_faces(ny, 2.0)
+    box = O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, yf, seed=0)
+    full = O.rk2_predictor(*(torch.tensor(q) for q in (u, v, w)), box, 1e-3, 1 / 550, 3 / 550)
+    wbox = O.Box(9, ny, 9, 9 * 2 * np.pi / nx, 9 * np.pi / nz, yf)
+    for i, k in [(0, 0), (31, 23), (10, 5)]:
+        xs = [(i + d) % nx for d in range(-4, 5)]
+        zs = [(k + d) % nz for d in range(-4, 5)]
+        win = [torch.tensor(np.ascontiguousarray(q[:, zs][:, :, xs])) for q in (u, v, w)]
+        ref = O.rk2_predictor(*win, wbox, 1e-3, 1 / 550, 3 / 550)
+        for a, b in zip(full, ref):
+            assert torch.equal(a[:, k, i], b[:, 4, 4])
+    # and a window of half-width one is not enough (the reach really is two)
+    xs = [(10 + d) % nx for d in range(-1, 2)]
+    zs = [(5 + d) % nz for d in range(-1, 2)]
+    win = [torch.tensor(np.ascontiguousarray(q[:, zs][:, :, xs])) for q in (u, v, w)]
+    ref = O.rk2_predictor(*win, O.Box(3, ny, 3, 3 * 2 * np.pi / nx, 3 * np.pi / nz, yf), 1e-3, 1 / 550, 3 / 550)
+    assert not torch.equal(full[0][:, 5, 10], ref[0][:, 1, 1])
