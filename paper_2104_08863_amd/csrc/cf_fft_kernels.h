@@ -124,7 +124,7 @@ struct XCfg {
   static constexpr int KWANT = int(128 / sizeof(cx<T>));
   static constexpr int S = lpad(NH) + 1;  // LDS row stride (holds kx = 0..NH at lpad(kx))
   static constexpr int kfit(int k) {
-    return (k > 1 && (k * S * int(sizeof(cx<T>)) > 73728 || k * FftT<NH>::TPL > 1024)) ? kfit(k / 2) : k;
+    return (k > 1 && (k * S * int(sizeof(cx<T>)) > 147456 || k * FftT<NH>::TPL > 1024)) ? kfit(k / 2) : k;
   }
   static constexpr int K = kfit(KWANT);
   static constexpr int THREADS = K * FftT<NH>::TPL;

@@ -20,6 +20,9 @@ CASES = [
     (128, 128, 96, 2.0, 8),
     (256, 96, 48, 2.5, 6),
     (32, 16, 2, 2.0, 1),
+    # long x rows: 8 (FP64) rows per x-transform block, a ragged last block in z
+    (2048, 8, 12, 2.0, 0),
+    (4096, 8, 6, 1.5, 0),
 ]
 
 
