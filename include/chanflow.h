@@ -149,6 +149,38 @@ cf_status cf_rk2_predictor(cf_plan* plan, const void* u, const void* v, const vo
                            void* ws, double dt, double nu, double fx, void* stream);
 
 /*
+ * Plane statistics of a velocity field (the quantities a channel-flow run
+ * averages, Section 5): for every y-plane j the means over the x-z plane of the
+ * stored u, v, w and of their squares, summed in FP64:
+ *   stats[6 j + 0..2] = <u>_j, <v>_j, <w>_j,  stats[6 j + 3..5] = <u^2>_j, <v^2>_j, <w^2>_j
+ * (v's plane j is the face above cell j; its top-wall plane is taken as stored).
+ * u, v, w as in cf_projection_step; stats: device double (ny, 6), overwritten.
+ * Bitwise repeatable (fixed reduction order, no atomics).
+ */
+cf_status cf_plane_stats(cf_plan* plan, const void* u, const void* v, const void* w, double* stats,
+                         void* stream);
+
+/*
+ * A time loop of nsteps projection steps (Section 2) starting from (u, v, w).
+ * The state alternates between (u, v, w) and the second set (u2, v2, w2) (same
+ * shape and precision, not overlapping the first), so every step writes
+ * separate arrays and takes the fused RK2 pass; the newest state ends in
+ * (u, v, w) when nsteps is even and in (u2, v2, w2) when it is odd.  After every
+ * stats_every-th step (0: never) the plane statistics of the new state (as in
+ * cf_plane_stats) are added into stats_acc (device double (ny, 6)); the caller
+ * clears it and divides by the number of samples.  p: optional device double
+ * (ny, nz, nx) receiving the last step's pressure, or NULL.
+ * use_graph != 0 records one step of each parity (with and without the
+ * statistics pass, as the loop needs them) into HIP graphs on a plan-owned
+ * stream and replays them, which removes the per-launch host cost; that mode
+ * returns after the work has finished.  Results are identical in both modes.
+ * The plan must have been created with CF_PLAN_STEP.
+ */
+cf_status cf_run_steps(cf_plan* plan, void* u, void* v, void* w, void* u2, void* v2, void* w2, int nsteps,
+                       double dt, double nu, double fx, int stats_every, double* stats_acc, double* p,
+                       int use_graph, void* stream);
+
+/*
  * Adjoint of cf_projection_step (the differentiated form of Section 2, Eq. (3)-(7)):
  * given the step input (u, v, w) and g1 = dJ/d(u1, v1, w1), returns
  * g = dJ/d(u, v, w) (Euclidean gradient, what autograd expects), with

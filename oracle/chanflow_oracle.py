@@ -327,6 +327,13 @@ def projection_step(u, v, w, box: Box, dt: float, nu: float, fx: float,
     return out
 
 
+
+def plane_stats(u, v, w):
+    """Per-plane means over the x-z plane of the stored u, v, w and of their
+    squares (the averages of a channel-flow run, Section 5): (ny, 6)."""
+    cols = [u, v, w, u * u, v * v, w * w]
+    return torch.stack([c.mean(dim=(1, 2)) for c in cols], dim=1)
+
 def rollout(u, v, w, box: Box, nsteps: int, dt: float, nu: float, fx: float):
     for _ in range(nsteps):
         u, v, w = projection_step(u, v, w, box, dt, nu, fx)
@@ -460,7 +467,7 @@ __all__ = [
     "Box", "y_coefficients", "modified_wavenumbers", "mean_w", "forward_transform",
     "inverse_transform", "thomas", "solve_spectral", "solve_mean_line", "poisson",
     "divergence", "gradient", "laplacian_p", "advection", "laplacian_vel",
-    "momentum_rhs", "rk2_predictor", "projection_step", "rollout", "rollout_loss_and_grad",
+    "momentum_rhs", "rk2_predictor", "projection_step", "plane_stats", "rollout", "rollout_loss_and_grad",
     "pdd_solve", "pdd_indicator", "line_coefficients", "set_threads",
 ]
 

@@ -48,6 +48,8 @@ SIGNATURES = {
     "cf_divergence": (_I, [_P, _P, _P, _P, _P, _D, _P]),
     "cf_projection_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
     "cf_rk2_predictor": (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
+    "cf_plane_stats": (_I, [_P, _P, _P, _P, _P, _P]),
+    "cf_run_steps": (_I, [_P, _P, _P, _P, _P, _P, _P, C.c_int, _D, _D, _D, C.c_int, _P, _P, C.c_int, _P]),
     "cf_projection_step_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),
     "cf_rhs_adjoint": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _D, _P]),
     "cf_forward_spectral": (_I, [_P, _P, _P, _P]),

@@ -169,6 +169,45 @@ class Plan:
                 "cf_rk2_predictor")
         return out
 
+    def plane_stats(self, u, v, w, out=None):
+        """Per-plane means of u, v, w and of their squares: a float64 (ny, 6)
+        tensor [<u>, <v>, <w>, <u^2>, <v^2>, <w^2>]."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w")):
+            self._field(t, n, sd)
+        if out is None:
+            out = torch.empty(self.ny, 6, dtype=torch.float64, device=self.device)
+        if out.shape != (self.ny, 6) or out.dtype != torch.float64 or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("stats must be a contiguous float64 (ny, 6) tensor on the plan's device")
+        L.check(L.lib().cf_plane_stats(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(out), _stream()), "cf_plane_stats")
+        return out
+
+    def run_steps(self, u, v, w, nsteps: int, dt: float, nu: float, fx: float, work=None,
+                  stats_every: int = 0, stats=None, p=None, use_graph: bool = False):
+        """A time loop of nsteps projection steps.  The state alternates between
+        (u, v, w) and `work` (three more arrays; allocated when None); returns the
+        newest state (u, v, w) or work, which holds it.  stats: float64 (ny, 6)
+        accumulator that gains the plane statistics after every stats_every-th
+        step.  use_graph: replay the steps from HIP graphs."""
+        sd = self.state_dtype
+        for t, n in ((u, "u"), (v, "v"), (w, "w")):
+            self._field(t, n, sd)
+        if work is None:
+            work = (self._new(sd), self._new(sd), self._new(sd))
+        for t, n in zip(work, ("u2", "v2", "w2")):
+            self._field(t, n, sd)
+        sp = None
+        if stats_every > 0:
+            if stats is None or stats.shape != (self.ny, 6) or stats.dtype != torch.float64 \
+                    or not stats.is_contiguous() or stats.device != self.device:
+                raise ValueError("stats must be a contiguous float64 (ny, 6) tensor on the plan's device")
+            sp = _ptr(stats)
+        pp = None if p is None else _ptr(self._field(p, "p"))
+        L.check(L.lib().cf_run_steps(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(work[0]), _ptr(work[1]),
+                                     _ptr(work[2]), int(nsteps), float(dt), float(nu), float(fx), int(stats_every),
+                                     sp, pp, int(bool(use_graph)), _stream()), "cf_run_steps")
+        return (u, v, w) if nsteps % 2 == 0 else tuple(work)
+
     def projection_step_adjoint(self, u, v, w, gu1, gv1, gw1, dt: float, nu: float, fx: float, out=None):
         """dJ/d(u, v, w) of one projection step from dJ/d(u1, v1, w1)."""
         sd = self.state_dtype

@@ -105,6 +105,10 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
 template <typename T>
 hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu,
                             T fx, hipStream_t s);
+// Per-plane means of u, v, w and their squares into st (ny, 6), or added to it.
+template <typename T>
+hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, const Geo<T>& g, int accumulate,
+                              hipStream_t s);
 template <typename T>
 hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s);
 

@@ -101,6 +101,10 @@ struct cf_plan {
   // side stream for the whole-line solves, which overlap the PDD kernel
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // stream on which step sequences are recorded into HIP graphs and replayed
+  // (capture needs a stream other than the legacy default one)
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
   // per-kernel event timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // created on demand, reused after each harvest
@@ -150,8 +154,11 @@ void free_all(cf_plan* pl) {
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
   if (pl->aux) (void)hipStreamDestroy(pl->aux);
-  pl->ev_fork = pl->ev_join = nullptr;
-  pl->aux = nullptr;
+  if (pl->ev_gin) (void)hipEventDestroy(pl->ev_gin);
+  if (pl->ev_gout) (void)hipEventDestroy(pl->ev_gout);
+  if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  pl->ev_fork = pl->ev_join = pl->ev_gin = pl->ev_gout = nullptr;
+  pl->aux = pl->gstream = nullptr;
 }
 
 hipError_t next_event(cf_plan* pl, hipEvent_t* ev) {
@@ -736,6 +743,9 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   e = hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_gin, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_gout, hipEventDisableTiming);
   if (e != hipSuccess) return bail(dev_fail(e, "stream/event creation"));
   if ((st = upload(pl, &pl->d_a, pl->a)) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->d_c, pl->c)) != CF_OK) return bail(st);
@@ -957,6 +967,135 @@ cf_status cf_rk2_predictor(cf_plan* pl, const void* u, const void* v, const void
   return rk2_t<double>(pl, static_cast<const double*>(u), static_cast<const double*>(v),
                        static_cast<const double*>(w), static_cast<double*>(us), static_cast<double*>(vs),
                        static_cast<double*>(ws), pl->g64, dt, nu, fx, s);
+}
+
+cf_status cf_plane_stats(cf_plan* pl, const void* u, const void* v, const void* w, double* stats, void* stream) {
+  CF_TRY(check_plan(pl));
+  const void* ptrs[4] = {u, v, w, stats};
+  const char* names[4] = {"u", "v", "w", "stats"};
+  for (int q = 0; q < 4; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = pl->mixed() ? cf::launch_plane_stats<float>(static_cast<const float*>(u), static_cast<const float*>(v),
+                                                             static_cast<const float*>(w), stats, pl->g32, 0, s)
+                             : cf::launch_plane_stats<double>(static_cast<const double*>(u),
+                                                              static_cast<const double*>(v),
+                                                              static_cast<const double*>(w), stats, pl->g64, 0, s);
+  if (e != hipSuccess) return dev_fail(e, "plane statistics launch");
+  return CF_OK;
+}
+
+namespace {
+
+// One step of the time loop from state a to state b (never the same arrays),
+// then, if wanted, the plane statistics of b added into acc.
+cf_status loop_step(cf_plan* pl, void* const a[3], void* const b[3], double* p, double dt, double nu, double fx,
+                    double* acc, hipStream_t s) {
+  if (pl->mixed()) {
+    CF_TRY(step_mixed(pl, static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
+                      static_cast<const float*>(a[2]), static_cast<float*>(b[0]), static_cast<float*>(b[1]),
+                      static_cast<float*>(b[2]), p, dt, nu, fx, s));
+    if (acc) {
+      const hipError_t e = cf::launch_plane_stats<float>(static_cast<const float*>(b[0]), static_cast<const float*>(b[1]),
+                                                         static_cast<const float*>(b[2]), acc, pl->g32, 1, s);
+      if (e != hipSuccess) return dev_fail(e, "plane statistics launch");
+    }
+    return CF_OK;
+  }
+  CF_TRY(step64(pl, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
+                static_cast<const double*>(a[2]), static_cast<double*>(b[0]), static_cast<double*>(b[1]),
+                static_cast<double*>(b[2]), p, dt, nu, fx, s));
+  if (acc) {
+    const hipError_t e = cf::launch_plane_stats<double>(static_cast<const double*>(b[0]),
+                                                        static_cast<const double*>(b[1]),
+                                                        static_cast<const double*>(b[2]), acc, pl->g64, 1, s);
+    if (e != hipSuccess) return dev_fail(e, "plane statistics launch");
+  }
+  return CF_OK;
+}
+
+// Records loop_step into an executable graph on the plan's capture stream.
+cf_status record_step(cf_plan* pl, void* const a[3], void* const b[3], double* p, double dt, double nu, double fx,
+                      double* acc, hipGraphExec_t* out) {
+  hipStream_t g = pl->gstream;
+  CF_HIP(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  const cf_status st = loop_step(pl, a, b, p, dt, nu, fx, acc, g);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g, &graph);
+  if (st != CF_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+  const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return dev_fail(ei, "hipGraphInstantiate");
+  return CF_OK;
+}
+
+}  // namespace
+
+cf_status cf_run_steps(cf_plan* pl, void* u, void* v, void* w, void* u2, void* v2, void* w2, int nsteps, double dt,
+                       double nu, double fx, int stats_every, double* stats_acc, double* p, int use_graph,
+                       void* stream) {
+  CF_TRY(check_plan(pl));
+  if (!(pl->opt.flags & CF_PLAN_STEP)) return fail(CF_ERR_ARG, "plan was created without CF_PLAN_STEP");
+  void* const A[3] = {u, v, w};
+  void* const B[3] = {u2, v2, w2};
+  const char* na[3] = {"u", "v", "w"};
+  const char* nb[3] = {"u2", "v2", "w2"};
+  for (int q = 0; q < 3; ++q) {
+    CF_TRY(check_ptr(A[q], na[q]));
+    CF_TRY(check_ptr(B[q], nb[q]));
+  }
+  const uintptr_t bytes = (uintptr_t)pl->nx * pl->ny * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const uintptr_t x = reinterpret_cast<uintptr_t>(A[a]), y = reinterpret_cast<uintptr_t>(B[b]);
+      if (x < y + bytes && y < x + bytes) return fail(CF_ERR_ARG, "the two state sets must not overlap");
+    }
+  if (nsteps < 0) return fail(CF_ERR_ARG, "nsteps must be >= 0");
+  if (stats_every < 0) return fail(CF_ERR_ARG, "stats_every must be >= 0");
+  if (stats_every > 0) CF_TRY(check_ptr(stats_acc, "stats_acc"));
+  if (p) CF_TRY(check_ptr(p, "p"));
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
+  if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto acc_at = [&](int step) -> double* { return (stats_every > 0 && (step + 1) % stats_every == 0) ? stats_acc : nullptr; };
+  if (!use_graph) {
+    for (int k = 0; k < nsteps; ++k) CF_TRY(loop_step(pl, (k & 1) ? B : A, (k & 1) ? A : B, p, dt, nu, fx, acc_at(k), s));
+    return CF_OK;
+  }
+  if (nsteps == 0) return CF_OK;
+  // four graphs: step A->B and B->A, each with and without the statistics pass
+  // (only the ones the loop uses are recorded); per-launch event timing is not
+  // recorded into graphs
+  const bool timing = pl->timing;
+  pl->timing = false;
+  hipGraphExec_t ex[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  cf_status st = CF_OK;
+  for (int k = 0; k < nsteps && st == CF_OK; ++k) {
+    const int par = k & 1, ws = acc_at(k) ? 1 : 0;
+    if (!ex[par][ws]) st = record_step(pl, par ? B : A, par ? A : B, p, dt, nu, fx, ws ? stats_acc : nullptr,
+                                       &ex[par][ws]);
+  }
+  pl->timing = timing;
+  hipError_t e = hipSuccess;
+  if (st == CF_OK) {
+    e = hipEventRecord(pl->ev_gin, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(pl->gstream, pl->ev_gin, 0);
+    for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = hipGraphLaunch(ex[k & 1][acc_at(k) ? 1 : 0], pl->gstream);
+    if (e == hipSuccess) e = hipEventRecord(pl->ev_gout, pl->gstream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, pl->ev_gout, 0);
+    // the executable graphs must outlive their launches
+    const hipError_t es = hipStreamSynchronize(pl->gstream);
+    if (e == hipSuccess) e = es;
+  }
+  for (auto& row : ex)
+    for (hipGraphExec_t g : row)
+      if (g) (void)hipGraphExecDestroy(g);
+  if (st != CF_OK) return st;
+  if (e != hipSuccess) return dev_fail(e, "graph replay");
+  return CF_OK;
 }
 
 cf_status cf_projection_step_adjoint(cf_plan* pl, const void* u, const void* v, const void* w,

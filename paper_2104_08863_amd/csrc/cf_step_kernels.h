@@ -314,4 +314,43 @@ k_correct(T* u, T* v, T* w, const double* __restrict__ p, Geo<T> g, T dt) {
   }
 }
 
+// Plane statistics of a velocity field: for every y-plane j the means over the
+// x-z plane of u, v, w and of their squares, summed in FP64.  One block per
+// plane and a fixed reduction order (strided per-thread sums, wave shuffles,
+// then the waves in order), so the result is bitwise repeatable.  st[j*6 + c]
+// receives (or, with accumulate, gains) the means.
+template <typename T, int TH>
+__global__ void __launch_bounds__(TH)
+k_plane_stats(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, double* __restrict__ st,
+              int nxz, double scale, int accumulate) {
+  __shared__ double red[6][TH / 64];
+  const long o = (long)blockIdx.x * nxz;
+  double sm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int e = threadIdx.x; e < nxz; e += TH) {
+    const double a = double(u[o + e]), b = double(v[o + e]), c = double(w[o + e]);
+    sm[0] += a;
+    sm[1] += b;
+    sm[2] += c;
+    sm[3] += a * a;
+    sm[4] += b * b;
+    sm[5] += c * c;
+  }
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    double x = sm[f];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
+    if ((threadIdx.x & 63) == 0) red[f][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double x = 0.0;
+    for (int k = 0; k < TH / 64; ++k) x += red[threadIdx.x][k];
+    x *= scale;
+    double* d = st + (long)blockIdx.x * 6 + threadIdx.x;
+    *d = accumulate ? *d + x : x;
+  }
+}
+
 }  // namespace cf

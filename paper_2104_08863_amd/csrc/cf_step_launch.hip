@@ -48,11 +48,22 @@ hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T 
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, const Geo<T>& g, int accumulate,
+                              hipStream_t s) {
+  const int nxz = g.nx * g.nz;
+  hipLaunchKernelGGL((k_plane_stats<T, 1024>), dim3(g.ny), dim3(1024), 0, s, u, v, w, st, nxz, 1.0 / double(nxz),
+                     accumulate);
+  return hipGetLastError();
+}
+
 #define CF_INST(T)                                                                                     \
   template hipError_t launch_rk_stage<T>(int, const T*, const T*, const T*, const T*, const T*,        \
                                          const T*, T*, T*, T*, const Geo<T>&, T, T, T, hipStream_t); \
   template hipError_t launch_rk2_fused<T>(const T*, const T*, const T*, T*, T*, T*, const Geo<T>&, T, T, T, \
                                           hipStream_t);                                                   \
+  template hipError_t launch_plane_stats<T>(const T*, const T*, const T*, double*, const Geo<T>&, int, \
+                                            hipStream_t);                                            \
   template hipError_t launch_correct<T>(T*, T*, T*, const double*, const Geo<T>&, T, hipStream_t);
 CF_INST(double)
 CF_INST(float)

@@ -99,5 +99,7 @@ def test_calls_reject_null_plan_and_pointers():
     assert lib.cf_inverse_spectral(None, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_divergence(None, p, p, p, p, 1.0, None) == L.CF_ERR_ARG
     assert lib.cf_rk2_predictor(None, p, p, p, p, p, p, 1e-3, 0.01, 0.0, None) == L.CF_ERR_ARG
+    assert lib.cf_plane_stats(None, p, p, p, p, None) == L.CF_ERR_ARG
+    assert lib.cf_run_steps(None, p, p, p, p, p, p, 1, 1e-3, 0.01, 0.0, 0, None, None, 0, None) == L.CF_ERR_ARG
     assert lib.cf_plan_query(None, None) == L.CF_ERR_ARG
     lib.cf_plan_destroy(None)

@@ -373,3 +373,25 @@ def test_rk2_predictor_reaches_two_cells_in_x_and_z():
     win = [torch.tensor(np.ascontiguousarray(q[:, zs][:, :, xs])) for q in (u, v, w)]
     ref = O.rk2_predictor(*win, O.Box(3, ny, 3, 3 * 2 * np.pi / nx, 3 * np.pi / nz, yf), 1e-3, 1 / 550, 3 / 550)
     assert not torch.equal(full[0][:, 5, 10], ref[0][:, 1, 1])
+
+
+def test_plane_stats_closed_forms():
+    """Per-plane means of constants and of one Fourier mode: <c> = c,
+    <sin> = 0 and <sin^2> = 1/2 exactly for a sampled full period."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    ny, nz, nx = 5, 6, 8
+    i = torch.arange(nx, dtype=torch.float64)
+    s = torch.sin(2 * np.pi * i / nx).expand(ny, nz, nx).clone()
+    c = torch.full((ny, nz, nx), 3.0, dtype=torch.float64)
+    ramp = torch.arange(ny, dtype=torch.float64)[:, None, None].expand(ny, nz, nx).clone()
+    st = O.plane_stats(s, c, ramp)
+    assert st.shape == (ny, 6)
+    assert torch.allclose(st[:, 0], torch.zeros(ny, dtype=torch.float64), atol=1e-15)
+    assert torch.allclose(st[:, 3], torch.full((ny,), 0.5, dtype=torch.float64), atol=1e-15)
+    assert torch.equal(st[:, 1], torch.full((ny,), 3.0, dtype=torch.float64))
+    assert torch.equal(st[:, 4], torch.full((ny,), 9.0, dtype=torch.float64))
+    assert torch.equal(st[:, 2], torch.arange(ny, dtype=torch.float64))
+    assert torch.equal(st[:, 5], torch.arange(ny, dtype=torch.float64) ** 2)
