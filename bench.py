@@ -178,6 +178,41 @@ def _time(fn, steps, warmup=2):
     return (time.perf_counter() - t0) / steps
 
 
+def time_loop_figures(wl, steps):
+    """The time loop (cf_run_steps) on the step grid, on the 256x128x256 rollout
+    grid and on a 64^3 grid (launch-bound: ~20 us of kernels per step), eager
+    and replayed from the plan's cached HIP graphs, with plane statistics after
+    every step (dt 1e-3, nu 1/550 on the small grids); and the statistics kernel
+    alone."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    res = {}
+    small = synth.Workload("loop64", 64, 64, 64, 2 * np.pi, np.pi, 2.0, nu=1.0 / 550.0, dt=1e-3, fx=3.0 / 550.0)
+    for w_ in (wl, synth.WORKLOADS["rollout256"], small):
+        yf = w_.y_faces()
+        pl = Plan(w_.nx, w_.ny, w_.nz, w_.lx, w_.lz, yf, precision="fp64", step=True)
+        st = [torch.tensor(q, device=dev) for q in synth.perturbed_poiseuille(w_.nx, w_.ny, w_.nz, yf, seed=0)]
+        work = tuple(torch.empty_like(t) for t in st)
+        acc = torch.zeros(w_.ny, 6, dtype=torch.float64, device=dev)
+        n = 10 if w_.npts > 1e7 else 50
+        fig = {"grid": [w_.nx, w_.ny, w_.nz], "steps_per_call": n}
+        for mode in ("eager", "graph"):
+            t = _time(lambda: pl.run_steps(*st, n, w_.dt, w_.nu, w_.fx, work=work, stats_every=1, stats=acc,
+                                           use_graph=(mode == "graph")), max(2, steps // 3), warmup=1)
+            fig[f"{mode}_ms_per_step"] = round(t * 1e3 / n, 4)
+            fig[f"{mode}_Mpts_s"] = round(w_.nx * w_.ny * w_.nz * n / t / 1e6, 1)
+        tst = _time(lambda: pl.plane_stats(*st), steps)
+        fig["plane_stats_us"] = round(tst * 1e6, 1)
+        fig["plane_stats_GBps"] = round(3 * 8 * w_.nx * w_.ny * w_.nz / tst / 1e9, 1)
+        res[f"time_loop_fp64_{w_.nx}x{w_.ny}x{w_.nz}"] = fig
+        del pl, st, work, acc
+        torch.cuda.empty_cache()
+    return res
+
+
 def secondary(wl, steps):
     """The other figures of the headline metric, each timed on resident inputs:
     FP64 vs mixed (FP32 + one FP64 refinement) Poisson solves on the step grid
@@ -221,6 +256,7 @@ def secondary(wl, steps):
                                     "Mpts_s": round(npts / t / 1e6, 1)}
     del pa, u, v, w, o, g1, go
     torch.cuda.empty_cache()
+    res.update(time_loop_figures(wl, steps))
     # mixed-precision Poisson solve on the Re_tau=1000-shaped grid
     big = synth.WORKLOADS["mixed1000"]
     nb = big.nx * big.ny * big.nz

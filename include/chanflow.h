@@ -170,10 +170,12 @@ cf_status cf_plane_stats(cf_plan* plan, const void* u, const void* v, const void
  * cf_plane_stats) are added into stats_acc (device double (ny, 6)); the caller
  * clears it and divides by the number of samples.  p: optional device double
  * (ny, nz, nx) receiving the last step's pressure, or NULL.
- * use_graph != 0 records one step of each parity (with and without the
- * statistics pass, as the loop needs them) into HIP graphs on a plan-owned
- * stream and replays them, which removes the per-launch host cost; that mode
- * returns after the work has finished.  Results are identical in both modes.
+ * use_graph != 0 replays the steps from HIP graphs on a plan-owned stream
+ * (ordered after earlier work on `stream`, and later work on `stream` after
+ * it): one recorded step per parity, with and without the statistics pass, kept
+ * in the plan (up to 8, least recently used dropped) and reused by later calls
+ * with the same arrays and parameters, which removes the per-launch host cost.
+ * Results are identical in both modes.
  * The plan must have been created with CF_PLAN_STEP.
  */
 cf_status cf_run_steps(cf_plan* plan, void* u, void* v, void* w, void* u2, void* v2, void* w2, int nsteps,

@@ -105,6 +105,18 @@ struct cf_plan {
   // (capture needs a stream other than the legacy default one)
   hipStream_t gstream = nullptr;
   hipEvent_t ev_gin = nullptr, ev_gout = nullptr;
+  // recorded loop steps, reused while the arrays and parameters repeat
+  struct GraphEntry {
+    void* a[3];
+    void* b[3];
+    double* p;
+    double* acc;
+    double dt, nu, fx;
+    hipGraphExec_t exec;
+    unsigned long long last_use;
+  };
+  std::vector<GraphEntry> graphs;
+  unsigned long long graph_clock = 0;
   // per-kernel event timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // created on demand, reused after each harvest
@@ -154,6 +166,8 @@ void free_all(cf_plan* pl) {
   if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
   if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
   if (pl->aux) (void)hipStreamDestroy(pl->aux);
+  for (auto& g : pl->graphs) (void)hipGraphExecDestroy(g.exec);
+  pl->graphs.clear();
   if (pl->ev_gin) (void)hipEventDestroy(pl->ev_gin);
   if (pl->ev_gout) (void)hipEventDestroy(pl->ev_gout);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
@@ -1066,34 +1080,68 @@ cf_status cf_run_steps(cf_plan* pl, void* u, void* v, void* w, void* u2, void* v
     return CF_OK;
   }
   if (nsteps == 0) return CF_OK;
-  // four graphs: step A->B and B->A, each with and without the statistics pass
-  // (only the ones the loop uses are recorded); per-launch event timing is not
-  // recorded into graphs
-  const bool timing = pl->timing;
-  pl->timing = false;
+  // One recorded step per (parity, statistics or not), found in or added to
+  // the plan's cache (at most kMaxGraphs entries; the least recently used one
+  // is dropped after the capture stream has drained).  Per-launch event timing
+  // is not recorded into graphs.
+  constexpr size_t kMaxGraphs = 8;
+  auto find = [&](void* const* a, void* const* b, double* acc) -> hipGraphExec_t {
+    for (auto& g : pl->graphs)
+      if (g.a[0] == a[0] && g.a[1] == a[1] && g.a[2] == a[2] && g.b[0] == b[0] && g.b[1] == b[1] &&
+          g.b[2] == b[2] && g.p == p && g.acc == acc && g.dt == dt && g.nu == nu && g.fx == fx) {
+        g.last_use = ++pl->graph_clock;
+        return g.exec;
+      }
+    return nullptr;
+  };
   hipGraphExec_t ex[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-  cf_status st = CF_OK;
-  for (int k = 0; k < nsteps && st == CF_OK; ++k) {
+  for (int k = 0; k < nsteps && k < 2 * (stats_every > 0 ? stats_every : 1); ++k) {
     const int par = k & 1, ws = acc_at(k) ? 1 : 0;
-    if (!ex[par][ws]) st = record_step(pl, par ? B : A, par ? A : B, p, dt, nu, fx, ws ? stats_acc : nullptr,
-                                       &ex[par][ws]);
+    if (ex[par][ws]) continue;
+    void* const* a = par ? B : A;
+    void* const* b = par ? A : B;
+    double* acc = ws ? stats_acc : nullptr;
+    ex[par][ws] = find(a, b, acc);
+    if (ex[par][ws]) continue;
+    if (pl->graphs.size() >= kMaxGraphs) {
+      CF_HIP(hipStreamSynchronize(pl->gstream), "hipStreamSynchronize");
+      size_t old = 0;
+      for (size_t q = 1; q < pl->graphs.size(); ++q)
+        if (pl->graphs[q].last_use < pl->graphs[old].last_use) old = q;
+      bool in_use = false;
+      for (auto& row : ex)
+        for (hipGraphExec_t g : row) in_use = in_use || g == pl->graphs[old].exec;
+      if (!in_use) {
+        (void)hipGraphExecDestroy(pl->graphs[old].exec);
+        pl->graphs.erase(pl->graphs.begin() + old);
+      }
+    }
+    const bool timing = pl->timing;
+    pl->timing = false;
+    hipGraphExec_t g = nullptr;
+    const cf_status st = record_step(pl, a, b, p, dt, nu, fx, acc, &g);
+    pl->timing = timing;
+    CF_TRY(st);
+    cf_plan::GraphEntry en;
+    for (int q = 0; q < 3; ++q) {
+      en.a[q] = a[q];
+      en.b[q] = b[q];
+    }
+    en.p = p;
+    en.acc = acc;
+    en.dt = dt;
+    en.nu = nu;
+    en.fx = fx;
+    en.exec = g;
+    en.last_use = ++pl->graph_clock;
+    pl->graphs.push_back(en);
+    ex[par][ws] = g;
   }
-  pl->timing = timing;
-  hipError_t e = hipSuccess;
-  if (st == CF_OK) {
-    e = hipEventRecord(pl->ev_gin, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(pl->gstream, pl->ev_gin, 0);
-    for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = hipGraphLaunch(ex[k & 1][acc_at(k) ? 1 : 0], pl->gstream);
-    if (e == hipSuccess) e = hipEventRecord(pl->ev_gout, pl->gstream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, pl->ev_gout, 0);
-    // the executable graphs must outlive their launches
-    const hipError_t es = hipStreamSynchronize(pl->gstream);
-    if (e == hipSuccess) e = es;
-  }
-  for (auto& row : ex)
-    for (hipGraphExec_t g : row)
-      if (g) (void)hipGraphExecDestroy(g);
-  if (st != CF_OK) return st;
+  hipError_t e = hipEventRecord(pl->ev_gin, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(pl->gstream, pl->ev_gin, 0);
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) e = hipGraphLaunch(ex[k & 1][acc_at(k) ? 1 : 0], pl->gstream);
+  if (e == hipSuccess) e = hipEventRecord(pl->ev_gout, pl->gstream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, pl->ev_gout, 0);
   if (e != hipSuccess) return dev_fail(e, "graph replay");
   return CF_OK;
 }

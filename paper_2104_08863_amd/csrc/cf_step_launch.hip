@@ -26,16 +26,25 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
 
 // Fused RK2 tile: 64 x 16 columns, one block of 16 waves per CU (stage 1 on the
 // 66 x 18 grown tile, whose 164 outer cells keep 3 of the 16 waves busy for one
-// more stencil pass), chunks of 128 planes.
-constexpr int RKF_TX = 64, RKF_TZ = 16, RKF_CY = 128;
+// more stencil pass).  Chunks of 128 planes; shorter chunks (32, then 8 planes)
+// when that leaves fewer than two blocks per CU, as on small grids.
+constexpr int RKF_TX = 64, RKF_TZ = 16;
 
 template <typename T>
 hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T* wo, const Geo<T>& g, T dt, T nu,
                             T fx, hipStream_t s) {
-  const long blocks = (long)((g.nx + RKF_TX - 1) / RKF_TX) * ((g.nz + RKF_TZ - 1) / RKF_TZ) *
-                      ((g.ny + RKF_CY - 1) / RKF_CY);
-  hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, RKF_CY>), dim3(blocks), dim3(RKF_TX * RKF_TZ), 0, s, u, v, w,
-                     uo, vo, wo, g, dt, nu, fx);
+  const long cols = (long)((g.nx + RKF_TX - 1) / RKF_TX) * ((g.nz + RKF_TZ - 1) / RKF_TZ);
+  auto blocks = [&](int cy) { return cols * ((g.ny + cy - 1) / cy); };
+  const dim3 th(RKF_TX * RKF_TZ);
+  if (blocks(128) >= 512)
+    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 128>), dim3(blocks(128)), th, 0, s, u, v, w, uo, vo, wo, g,
+                       dt, nu, fx);
+  else if (blocks(32) >= 512)
+    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 32>), dim3(blocks(32)), th, 0, s, u, v, w, uo, vo, wo, g, dt,
+                       nu, fx);
+  else
+    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 8>), dim3(blocks(8)), th, 0, s, u, v, w, uo, vo, wo, g, dt,
+                       nu, fx);
   return hipGetLastError();
 }
 
