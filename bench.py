@@ -213,6 +213,34 @@ def time_loop_figures(wl, steps):
     return res
 
 
+def rollout_figure(steps):
+    """The differentiable-rollout workload: 8 FP64 projection steps on
+    256x128x256 through the autograd Function (checkpoints every 2 steps), loss
+    0.5 sum(u^2 + v^2 + w^2), backward to the initial field; ms per step of
+    forward + adjoint."""
+    import torch
+
+    from paper_2104_08863_amd import autograd as AG
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    w_ = synth.WORKLOADS["rollout256"]
+    yf = w_.y_faces()
+    pl = Plan(w_.nx, w_.ny, w_.nz, w_.lx, w_.lz, yf, precision="fp64", adjoint=True)
+    init = [torch.tensor(q, device=dev) for q in synth.perturbed_poiseuille(w_.nx, w_.ny, w_.nz, yf, seed=0)]
+
+    def run():
+        xs = [t.clone().requires_grad_(True) for t in init]
+        a, b, c = AG.rollout(pl, *xs, 8, w_.dt, w_.nu, w_.fx, checkpoint_every=2)
+        (0.5 * ((a * a).sum() + (b * b).sum() + (c * c).sum())).backward()
+    t = _time(run, max(2, steps // 2), warmup=1)
+    del pl, init
+    torch.cuda.empty_cache()
+    return {"rollout_fwd_adjoint_fp64_256x128x256": {
+        "grid": [w_.nx, w_.ny, w_.nz], "steps": 8, "checkpoint_every": 2,
+        "ms_per_step": round(t * 1e3 / 8, 4), "ms_per_rollout": round(t * 1e3, 3)}}
+
+
 def secondary(wl, steps):
     """The other figures of the headline metric, each timed on resident inputs:
     FP64 vs mixed (FP32 + one FP64 refinement) Poisson solves on the step grid
@@ -257,6 +285,7 @@ def secondary(wl, steps):
     del pa, u, v, w, o, g1, go
     torch.cuda.empty_cache()
     res.update(time_loop_figures(wl, steps))
+    res.update(rollout_figure(steps))
     # mixed-precision Poisson solve on the Re_tau=1000-shaped grid
     big = synth.WORKLOADS["mixed1000"]
     nb = big.nx * big.ny * big.nz
