@@ -18,7 +18,7 @@ CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMER
 CF_FP64, CF_MIXED = 0, 1
 KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
            "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted", "rk2_fused"]
-CF_PLAN_STEP, CF_PLAN_ADJOINT = 1, 2
+CF_PLAN_STEP, CF_PLAN_ADJOINT, CF_PLAN_Y_DCT = 1, 2, 4
 
 
 class cf_options(C.Structure):

@@ -20,12 +20,14 @@ def _ptr(t: torch.Tensor):
 
 class Plan:
     """Plan for one grid: nx x ny x nz cells, periodic lengths lx, lz, wall-normal
-    faces y_faces (ny+1 values).  precision: 'fp64' or 'mixed'."""
+    faces y_faces (ny+1 values).  precision: 'fp64' or 'mixed'.  y_solver:
+    'pdd' (partitioned tridiagonal solve) or 'dct' (transform along y; uniform
+    faces and FP64 only)."""
 
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
                  precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
                  fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
-                 step: bool = False, adjoint: bool = False, device=None):
+                 step: bool = False, adjoint: bool = False, y_solver: str = "pdd", device=None):
         lib = L.lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nkx = self.nx // 2 + 1
@@ -45,7 +47,10 @@ class Plan:
         opt.fp64_kx = int(fp64_kx)
         opt.fp64_kz = int(fp64_kz)
         opt.refine_passes = int(refine_passes)
-        opt.flags = (L.CF_PLAN_STEP if (step or adjoint) else 0) | (L.CF_PLAN_ADJOINT if adjoint else 0)
+        if y_solver not in ("pdd", "dct"):
+            raise ValueError("y_solver must be 'pdd' or 'dct'")
+        opt.flags = (L.CF_PLAN_STEP if (step or adjoint) else 0) | (L.CF_PLAN_ADJOINT if adjoint else 0) \
+            | (L.CF_PLAN_Y_DCT if y_solver == "dct" else 0)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):

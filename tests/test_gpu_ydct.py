@@ -1,0 +1,83 @@
+"""Uniform-y variant: the wall-normal systems solved by the FFT of each line's
+even extension (CF_PLAN_Y_DCT) against the FP64 oracle and the tridiagonal
+path on the same uniform grids."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def plans(nx, ny, nz, **kw):
+    from paper_2104_08863_amd.api import Plan
+    yf = np.linspace(-1.0, 1.0, ny + 1)
+    mk = lambda solver: Plan(nx, ny, nz, 2 * np.pi, np.pi, yf, y_solver=solver, **kw)  # noqa: E731
+    return mk, O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(64, 64, 64), (96, 48, 24), (32, 8, 6), (128, 256, 96), (16, 512, 8),
+                                      (8, 1024, 4), (16, 3, 12)])
+def test_poisson_dct_matches_oracle_and_tridiagonal(nx, ny, nz):
+    """Tolerance: two correct FP64 solvers of the same system differ by up to
+    the line operator's condition number times the unit round-off; on a uniform
+    grid that is 1/sin^2(pi/2ny) (the ratio of its largest to its smallest
+    non-zero eigenvalue), 2.7e4 for ny = 256, so the 1e-12 of the tridiagonal
+    path is raised to 2 kappa eps where that is larger."""
+    mk, box = plans(nx, ny, nz)
+    kappa = 1.0 / np.sin(np.pi / (2 * ny)) ** 2
+    tol = max(1e-12, 2 * kappa * np.finfo(np.float64).eps)
+    f = synth.uniform_rhs(nx, ny, nz, seed=4)
+    ref = O.poisson(torch.tensor(f), box).numpy()
+    fg = torch.tensor(f, device=dev())
+    p_dct = mk("dct").poisson_solve(fg).cpu().numpy()
+    p_pdd = mk("pdd").poisson_solve(fg).cpu().numpy()
+    e_ref, e_pdd = rel(p_dct, ref), rel(p_dct, p_pdd)
+    print(f"{nx}x{ny}x{nz}: dct vs oracle {e_ref:.2e}, vs tridiagonal {e_pdd:.2e}, tolerance {tol:.1e}")
+    assert e_ref <= tol
+    assert e_pdd <= tol
+    # in place
+    g = fg.clone()
+    pl = mk("dct")
+    pl.poisson_solve(g, out=g)
+    assert np.array_equal(g.cpu().numpy(), pl.poisson_solve(fg).cpu().numpy())
+
+
+def test_step_and_adjoint_with_dct_match_oracle():
+    nx, ny, nz = 32, 32, 24
+    mk, box = plans(nx, ny, nz, adjoint=True)
+    pl = mk("dct")
+    dt, nu = 1e-3, 1 / 550
+    u, v, w = synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=6)
+    ut = [torch.tensor(q, requires_grad=True) for q in (u, v, w)]
+    out = O.projection_step(*ut, box, dt, nu, 3 * nu)
+    g1 = synth.random_directions(nx, ny, nz, seed=7)
+    ref_g = torch.autograd.grad(out, ut, grad_outputs=[torch.tensor(q) for q in g1])
+    ug = [torch.tensor(q, device=dev()) for q in (u, v, w)]
+    got = pl.projection_step(*ug, dt, nu, 3 * nu)
+    for a, b in zip(got, out):
+        assert rel(a.cpu().numpy(), b.detach().numpy()) <= 1e-12
+    gg = pl.projection_step_adjoint(*ug, *(torch.tensor(q, device=dev()) for q in g1), dt, nu, 3 * nu)
+    for a, b in zip(gg, ref_g):
+        assert rel(a.cpu().numpy(), b.numpy()) <= 1e-10
+
+
+def test_dct_rejects_unsupported_plans():
+    from paper_2104_08863_amd.api import Plan
+    from paper_2104_08863_amd._lib import ChanflowError
+    with pytest.raises(ChanflowError):          # stretched faces
+        Plan(16, 16, 8, 1.0, 1.0, synth.tanh_faces(16, 2.0), y_solver="dct")
+    with pytest.raises(ChanflowError):          # FP64 only
+        Plan(16, 16, 8, 1.0, 1.0, np.linspace(-1, 1, 17), precision="mixed", y_solver="dct")
+    with pytest.raises(ChanflowError):          # 2 ny = 10 is not a transform length
+        Plan(16, 5, 8, 1.0, 1.0, np.linspace(-1, 1, 6), y_solver="dct")

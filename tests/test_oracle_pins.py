@@ -395,3 +395,35 @@ def test_plane_stats_closed_forms():
     assert torch.equal(st[:, 4], torch.full((ny,), 9.0, dtype=torch.float64))
     assert torch.equal(st[:, 2], torch.arange(ny, dtype=torch.float64))
     assert torch.equal(st[:, 5], torch.arange(ny, dtype=torch.float64) ** 2)
+
+
+def test_uniform_y_solve_is_a_periodic_solve_of_the_even_extension():
+    """On a uniform y grid the staggered wall-normal operator with no wall flux
+    is the periodic second difference on the 2ny-point even extension: the
+    oracle's Thomas solve (gauge of the kx = kz = 0 line included) equals a
+    numpy FFT solve of the extended lines.  The GPU y-transform path is built on
+    this identity."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    nx, ny, nz = 8, 12, 6
+    yf = np.linspace(-1.0, 1.0, ny + 1)
+    box = O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+    rng = np.random.default_rng(3)
+    f = rng.uniform(-1, 1, size=(ny, nz, nx))
+    ref = O.poisson(torch.tensor(f), box).numpy()
+    dx, dz, dy = 2 * np.pi / nx, np.pi / nz, 2.0 / ny
+    fh = np.fft.fft(np.fft.fft(f, axis=2), axis=1)           # (ny, nz, nx)
+    ext = np.concatenate([fh, fh[::-1]], axis=0)              # even extension in y
+    eh = np.fft.fft(ext, axis=0)
+    m = np.arange(2 * ny)
+    lam_y = -(2 * np.sin(np.pi * m / (2 * ny)) / dy) ** 2
+    kx2 = (2 * np.sin(np.pi * np.arange(nx) / nx) / dx) ** 2
+    kz2 = (2 * np.sin(np.pi * np.arange(nz) / nz) / dz) ** 2
+    mu = lam_y[:, None, None] - kz2[None, :, None] - kx2[None, None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ph = np.where(mu == 0, 0.0, eh / mu)
+    p = np.fft.ifft(ph, axis=0)[:ny]
+    p = np.fft.ifft(np.fft.ifft(p, axis=1), axis=2).real
+    assert np.abs(p - ref).max() <= 1e-12 * np.abs(ref).max()
