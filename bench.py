@@ -269,6 +269,22 @@ def secondary(wl, steps):
                                     "rel_l2_vs_fp64_gpu": err}
     del pm, pmx, p64, f
     torch.cuda.empty_cache()
+    # uniform y faces: tridiagonal (PDD) path vs the y-transform path
+    yu = np.linspace(-1.0, 1.0, wl.ny + 1)
+    fu = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0), device=dev)
+    pu = {}
+    for solver in ("pdd", "dct"):
+        plu = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yu, precision="fp64", y_solver=solver)
+        out_u = torch.empty_like(fu)
+        t = _time(lambda: plu.poisson_solve(fu, out=out_u), steps)
+        pu[solver] = out_u
+        res[f"poisson_fp64_uniform_y_{solver}"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
+                                                   "Mpts_s": round(npts / t / 1e6, 1)}
+        del plu
+    res["poisson_fp64_uniform_y_dct"]["rel_l2_vs_pdd"] = float(
+        torch.linalg.vector_norm(pu["dct"] - pu["pdd"]) / torch.linalg.vector_norm(pu["pdd"]))
+    del pu, fu
+    torch.cuda.empty_cache()
     # forward + adjoint step, FP64
     pa = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64", adjoint=True)
     u, v, w = (torch.tensor(q, device=dev) for q in synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0))
