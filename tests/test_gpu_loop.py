@@ -98,3 +98,32 @@ def test_run_steps_rejects_overlapping_state_sets():
         pl.run_steps(u, v, w, 2, 1e-3, 1 / 550, 3 / 550, work=(v, u, w))
     with pytest.raises(ChanflowError):
         pl.run_steps(u, v, w, -1, 1e-3, 1 / 550, 3 / 550)
+
+
+def test_graph_cache_eviction_and_pressure_output():
+    """More distinct (arrays, parameters) sets than the plan keeps recorded
+    steps for: entries are dropped and re-recorded, results stay equal to the
+    eager loop; the optional pressure output receives the last step's p."""
+    pl, box = setup(32, 16, 24, 2.0)
+    dt, nu = 1e-3, 1 / 550
+    u, v, w = state(pl, box, 5)
+    for rep in range(2):
+        for k in range(6):                       # 6 parameter sets x 2 parities > 8 entries
+            g = [t.clone() for t in (u, v, w)]
+            gw = tuple(torch.empty_like(t) for t in g)
+            got = pl.run_steps(*g, 2, dt * (1 + 0.1 * k), nu, 3 * nu, work=gw, use_graph=True)
+            e = [t.clone() for t in (u, v, w)]
+            want = pl.run_steps(*e, 2, dt * (1 + 0.1 * k), nu, 3 * nu, work=tuple(torch.empty_like(t) for t in e))
+            for x, y in zip(got, want):
+                assert torch.equal(x, y), f"rep {rep} set {k}"
+    p = torch.empty_like(u)
+    a = [t.clone() for t in (u, v, w)]
+    out = pl.run_steps(*a, 3, dt, nu, 3 * nu, p=p)
+    b = [t.clone() for t in (u, v, w)]
+    for _ in range(2):
+        b = list(pl.projection_step(*b, dt, nu, 3 * nu))
+    p_ref = torch.empty_like(u)
+    b = pl.projection_step(*b, dt, nu, 3 * nu, p=p_ref)
+    assert torch.equal(p, p_ref)
+    for x, y in zip(out, b):
+        assert torch.equal(x, y)
