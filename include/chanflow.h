@@ -72,7 +72,7 @@ typedef struct {
 /* CF_PLAN_Y_DCT: solve the wall-normal systems by a transform along y instead of
    the partitioned tridiagonal solve (the fully spectral variant for uniform
    spacing, Section 2.1).  Needs uniform y faces (spacing equal to 1e-12
-   relative), CF_FP64, and 2*ny of the form 2^a or 3*2^a, at most 2048. */
+   relative), CF_FP64, and an even ny of the form 2^a or 3*2^a, at most 2048. */
 enum { CF_PLAN_STEP = 1, CF_PLAN_ADJOINT = 2, CF_PLAN_Y_DCT = 4 };
 
 typedef struct {

@@ -109,12 +109,13 @@ hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T*
 template <typename T>
 hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, const Geo<T>& g, int accumulate,
                               hipStream_t s);
-// Uniform-y wall-normal solve by the FFT of each line's even extension
-// (length 2 ny); in place allowed.
-bool ydct_len_compiled(int n2);
+// Uniform-y wall-normal solve by a DCT-II / DCT-III pair along y (N-point
+// FFTs, N = ny even); in place allowed.  tw: FFT twiddles of length ny;
+// wq: exp(-i pi m / 2ny), m < ny; lam: -(2 sin(pi m / 2ny) / dy)^2, m <= ny.
+bool ydct_len_compiled(int n);
 template <typename T>
-hipError_t launch_ydct(const cx<T>* fin, cx<T>* pout, const cx<T>* tw, const T* lam, const T* kx2, const T* kz2,
-                       int ny, int nz, int nkx, hipStream_t s);
+hipError_t launch_ydct(const cx<T>* fin, cx<T>* pout, const cx<T>* tw, const cx<T>* wq, const T* lam,
+                       const T* kx2, const T* kz2, int ny, int nz, int nkx, hipStream_t s);
 template <typename T>
 hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, hipStream_t s);
 

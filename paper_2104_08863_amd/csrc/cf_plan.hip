@@ -76,9 +76,11 @@ struct cf_plan {
   float *s_rdy = nullptr, *s_rdyc = nullptr, *s_wl = nullptr, *s_wu = nullptr;
   float *s_a = nullptr, *s_c = nullptr, *s_kx2 = nullptr, *s_kz2 = nullptr;
   cx<double>*tw_z64 = nullptr, *tw_x64 = nullptr, *twp64 = nullptr;
-  // uniform-y transform solve (CF_PLAN_Y_DCT): twiddles of length 2 ny and the
-  // y eigenvalues -(2 sin(pi m / 2ny) / dy)^2, m = 0..ny
+  // uniform-y transform solve (CF_PLAN_Y_DCT): FFT twiddles of length ny, the
+  // DCT twiddles exp(-i pi m / 2ny) and the y eigenvalues
+  // -(2 sin(pi m / 2ny) / dy)^2, m = 0..ny
   cx<double>* tw_y64 = nullptr;
+  cx<double>* d_wqy = nullptr;
   double* d_lamy = nullptr;
   cx<float>*tw_z32 = nullptr, *tw_x32 = nullptr, *twp32 = nullptr;
   int* d_special = nullptr;
@@ -368,8 +370,8 @@ cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
   if constexpr (std::is_same<T, double>::value) {
     if (pl->opt.flags & CF_PLAN_Y_DCT)
       return timed(pl, CF_K_YSOLVE, s, "y-transform solve launch", [&] {
-        return cf::launch_ydct<double>(fin, pout, pl->tw_y64, pl->d_lamy, pl->d_kx2, pl->d_kz2, pl->ny, pl->nz,
-                                       pl->nkx, s);
+        return cf::launch_ydct<double>(fin, pout, pl->tw_y64, pl->d_wqy, pl->d_lamy, pl->d_kx2, pl->d_kz2, pl->ny,
+                                       pl->nz, pl->nkx, s);
       });
   }
   cf::YLaunch y;
@@ -668,7 +670,8 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   if (opt.drop_tol < 0) opt.drop_tol = (opt.precision == CF_MIXED) ? 1e-7 : 1e-15;
   if (opt.flags & CF_PLAN_Y_DCT) {
     if (opt.precision != CF_FP64) return fail(CF_ERR_UNSUPPORTED, "the y-transform solve is FP64 only");
-    if (!cf::ydct_len_compiled(2 * ny)) return fail(CF_ERR_UNSUPPORTED, "the y-transform solve needs 2*ny = 2^a or 3*2^a <= 2048");
+    if (ny % 2 != 0 || !cf::ydct_len_compiled(ny))
+      return fail(CF_ERR_UNSUPPORTED, "the y-transform solve needs an even ny = 2^a or 3*2^a <= 2048");
     const double d0 = y_faces[1] - y_faces[0];
     for (int j = 0; j < ny; ++j)
       if (std::fabs((y_faces[j + 1] - y_faces[j]) - d0) > 1e-12 * d0)
@@ -807,8 +810,9 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   if ((st = upload(pl, &pl->tw_x32, tofc(twx))) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->twp32, tofc(twp))) != CF_OK) return bail(st);
   if (opt.flags & CF_PLAN_Y_DCT) {
-    std::vector<cx<double>> twy(2 * ny);
-    for (int m = 0; m < 2 * ny; ++m) twy[m] = unit_root(m, 2 * ny);
+    std::vector<cx<double>> twy(ny), wqy(ny);
+    for (int m = 0; m < ny; ++m) twy[m] = unit_root(m, ny);
+    for (int m = 0; m < ny; ++m) wqy[m] = unit_root(m, 4 * ny);
     // dy as the mean spacing (the faces are uniform to 1e-12)
     const double dyu = (pl->yf[ny] - pl->yf[0]) / ny;
     std::vector<double> lamy(ny + 1);
@@ -817,6 +821,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
       lamy[m] = -(2.0 * sn / dyu) * (2.0 * sn / dyu);
     }
     if ((st = upload(pl, &pl->tw_y64, twy)) != CF_OK) return bail(st);
+    if ((st = upload(pl, &pl->d_wqy, wqy)) != CF_OK) return bail(st);
     if ((st = upload(pl, &pl->d_lamy, lamy)) != CF_OK) return bail(st);
   }
   {
