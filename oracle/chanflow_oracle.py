@@ -17,7 +17,7 @@ What it computes, following the paper (arXiv 2104.08863):
     correction) -- kept here as the approximation the GPU drop path reproduces;
     the plain Thomas solve is the exact definition used for the pressure.
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
   * y is wall-normal, z spanwise (Section 5 naming);
   * Eq. (9): the middle coefficient is -2 (the printed +2 is a sign garble);
   * steps (6) and (8) of Section 3.2 are inverse transforms;
@@ -28,7 +28,9 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
   * momentum RHS: divergence (flux) form with linear interpolation, Laplacian
     with the no-slip ghost mirrored about the wall (parity of this part is
     pinned by conservation, Galilean and convergence properties, not by
-    values printed in the paper).
+    values printed in the paper);
+  * per-plane statistics: plain means over the x-z plane of the stored
+    (staggered) u, v, w and their squares.
 
 Array layout: physical (ny, nz, nx); spectrum (ny, nz, nx//2+1).
 """
