@@ -1,11 +1,12 @@
-// Launch of the RK2 momentum stages and the pressure-gradient correction.
+// Launch of the RK2 momentum stages, the pressure-gradient correction and the
+// plane statistics.
 #include "cf_internal.h"
 #include "cf_rk_fused.h"
 #include "cf_step_kernels.h"
 
 namespace cf {
 
-// Tile: 64 x 8 columns, chunks of 32 planes.
+// Split-stage tile: 64 x 8 columns, chunks of 32 planes.
 constexpr int RK_TX = 64, RK_TZ = 8, RK_CY = 32;
 
 template <typename T>
