@@ -241,6 +241,48 @@ def rollout_figure(steps):
         "ms_per_step": round(t * 1e3 / 8, 4), "ms_per_rollout": round(t * 1e3, 3)}}
 
 
+def fwd_adjoint_mixed(steps: int = 2, warmup: int = 1):
+    """Mixed-precision forward + adjoint step on the 2048x768x2048 grid (FP32
+    state; the gradient overwrites the incoming adjoint field): perturbed
+    Poiseuille state and an N(0, 0.1^2) adjoint field from a seeded torch CUDA
+    generator."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    c5 = synth.WORKLOADS["adj2000"]
+    n5 = c5.nx * c5.ny * c5.nz
+    y5 = c5.y_faces()
+    yc = torch.tensor(0.5 * (y5[1:] + y5[:-1]), dtype=torch.float32, device=dev)
+    shp = (c5.ny, c5.nz, c5.nx)
+
+    def gauss():
+        return torch.randn(shp, dtype=torch.float32, device=dev, generator=gen) * 0.1
+    u = gauss() + (1.5 * (1 - yc * yc))[:, None, None]
+    v = gauss()
+    v[-1] = 0
+    w = gauss()
+    o = tuple(torch.empty_like(u) for _ in range(3))
+    g = (gauss(), gauss(), gauss())
+    pm = Plan(c5.nx, c5.ny, c5.nz, c5.lx, c5.lz, y5, precision="mixed", adjoint=True)
+
+    def fwd_adj5():
+        pm.projection_step(u, v, w, c5.dt, c5.nu, c5.fx, out=o)
+        pm.projection_step_adjoint(u, v, w, *g, c5.dt, c5.nu, c5.fx, out=g)
+    t = _time(fwd_adj5, steps, warmup=warmup)
+    finite = bool(torch.isfinite(g[0]).all() and torch.isfinite(o[0]).all())
+    res = {"fwd_adjoint_step_mixed_2048x768x2048": {
+        "grid": [c5.nx, c5.ny, c5.nz], "ms": round(t * 1e3, 2), "Mpts_s": round(n5 / t / 1e6, 1),
+        "finite": finite, "plan_workspace_GB": round(pm.info()["workspace_bytes"] / 1e9, 1),
+        "input": "perturbed Poiseuille (seeded torch CUDA generator), FP32 state"}}
+    del pm, u, v, w, o, g
+    torch.cuda.empty_cache()
+    return res
+
+
 def secondary(wl, steps):
     """The other figures of the headline metric, each timed on resident inputs:
     FP64 vs mixed (FP32 + one FP64 refinement) Poisson solves on the step grid
@@ -316,36 +358,7 @@ def secondary(wl, steps):
         "input": "uniform[-1,1] RHS from a seeded torch CUDA generator"}
     del pm, pb, fb
     torch.cuda.empty_cache()
-    # mixed-precision forward + adjoint step on the Re_tau=2000-shaped grid
-    # (FP32 state; the gradient overwrites the incoming adjoint field)
-    c5 = synth.WORKLOADS["adj2000"]
-    n5 = c5.nx * c5.ny * c5.nz
-    y5 = c5.y_faces()
-    yc = torch.tensor(0.5 * (y5[1:] + y5[:-1]), dtype=torch.float32, device=dev)
-    gen.manual_seed(0)
-    shp = (c5.ny, c5.nz, c5.nx)
-
-    def gauss():
-        return torch.randn(shp, dtype=torch.float32, device=dev, generator=gen) * 0.1
-    u = gauss() + (1.5 * (1 - yc * yc))[:, None, None]
-    v = gauss()
-    v[-1] = 0
-    w = gauss()
-    o = tuple(torch.empty_like(u) for _ in range(3))
-    g = (gauss(), gauss(), gauss())
-    pm = Plan(c5.nx, c5.ny, c5.nz, c5.lx, c5.lz, y5, precision="mixed", adjoint=True)
-
-    def fwd_adj5():
-        pm.projection_step(u, v, w, c5.dt, c5.nu, c5.fx, out=o)
-        pm.projection_step_adjoint(u, v, w, *g, c5.dt, c5.nu, c5.fx, out=g)
-    t = _time(fwd_adj5, 2, warmup=1)
-    finite = bool(torch.isfinite(g[0]).all() and torch.isfinite(o[0]).all())
-    res["fwd_adjoint_step_mixed_2048x768x2048"] = {
-        "grid": [c5.nx, c5.ny, c5.nz], "ms": round(t * 1e3, 2), "Mpts_s": round(n5 / t / 1e6, 1),
-        "finite": finite, "plan_workspace_GB": round(pm.info()["workspace_bytes"] / 1e9, 1),
-        "input": "perturbed Poiseuille (seeded torch CUDA generator), FP32 state"}
-    del pm, u, v, w, o, g
-    torch.cuda.empty_cache()
+    res.update(fwd_adjoint_mixed(steps=2, warmup=1))
     return res
 
 
@@ -362,6 +375,9 @@ def main():
                     help="time the Poisson solve alone instead of the projection step")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="print the traffic table of rocprofv3 --pmc passes and exit")
     ap.add_argument("--summarize-trace", metavar="CSV", help="print a rocprofv3 kernel_stats.csv as markdown and exit")
+    ap.add_argument("--profile-fwd-adjoint-mixed", action="store_true",
+                    help="only run two mixed-precision forward + adjoint steps on 2048x768x2048 (for a "
+                         "profiler) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain elementwise kernel reading and writing BYTES bytes "
                          "three times (reference for hardware traffic counters) and exit")
@@ -371,6 +387,9 @@ def main():
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
+        return
+    if args.profile_fwd_adjoint_mixed:
+        fwd_adjoint_mixed(steps=2, warmup=0)
         return
     if args.calibrate_copy:
         import torch
