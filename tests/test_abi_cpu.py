@@ -89,6 +89,19 @@ def test_plan_rejects_bad_grid_and_options():
     assert L.lib().cf_plan_create(None, 16, 8, 8, 1.0, 1.0, yf.ctypes.data_as(C.POINTER(C.c_double)), None) == L.CF_ERR_ARG
 
 
+def test_plan_rejects_unsupported_y_transform_solve():
+    opt = L.cf_options()
+    L.lib().cf_options_default(C.byref(opt))
+    opt.flags = L.CF_PLAN_Y_DCT
+    yf = np.linspace(-1, 1, 17)
+    stretched = np.tanh(2.0 * np.linspace(-1, 1, 17)) / np.tanh(2.0)
+    assert _create(16, 16, 8, stretched, opt)[0] == L.CF_ERR_ARG            # not uniform
+    assert _create(16, 3, 8, np.linspace(-1, 1, 4), opt)[0] == L.CF_ERR_UNSUPPORTED   # odd ny
+    assert _create(16, 20, 8, np.linspace(-1, 1, 21), opt)[0] == L.CF_ERR_UNSUPPORTED  # 20 not 2^a, 3*2^a
+    opt.precision = L.CF_MIXED
+    assert _create(16, 16, 8, yf, opt)[0] == L.CF_ERR_UNSUPPORTED           # FP64 only
+
+
 def test_calls_reject_null_plan_and_pointers():
     lib = L.lib()
     buf = (C.c_double * 8)()
