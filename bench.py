@@ -182,8 +182,8 @@ def time_loop_figures(wl, steps):
     """The time loop (cf_run_steps) on the step grid, on the 256x128x256 rollout
     grid and on a 64^3 grid (launch-bound: ~20 us of kernels per step), eager
     and replayed from the plan's cached HIP graphs, with plane statistics after
-    every step (dt 1e-3, nu 1/550 on the small grids); and the statistics kernel
-    alone."""
+    every step (dt 1e-3, nu 1/550 on the small grids) and without statistics;
+    and the statistics kernel alone."""
     import torch
 
     from paper_2104_08863_amd import synth
@@ -199,11 +199,13 @@ def time_loop_figures(wl, steps):
         acc = torch.zeros(w_.ny, 6, dtype=torch.float64, device=dev)
         n = 10 if w_.npts > 1e7 else 50
         fig = {"grid": [w_.nx, w_.ny, w_.nz], "steps_per_call": n}
-        for mode in ("eager", "graph"):
-            t = _time(lambda: pl.run_steps(*st, n, w_.dt, w_.nu, w_.fx, work=work, stats_every=1, stats=acc,
-                                           use_graph=(mode == "graph")), max(2, steps // 3), warmup=1)
-            fig[f"{mode}_ms_per_step"] = round(t * 1e3 / n, 4)
-            fig[f"{mode}_Mpts_s"] = round(w_.nx * w_.ny * w_.nz * n / t / 1e6, 1)
+        for every, tag in ((1, ""), (0, "nostats_")):
+            for mode in ("eager", "graph"):
+                t = _time(lambda: pl.run_steps(*st, n, w_.dt, w_.nu, w_.fx, work=work, stats_every=every,
+                                               stats=acc if every else None, use_graph=(mode == "graph")),
+                          max(2, steps // 3), warmup=1)
+                fig[f"{tag}{mode}_ms_per_step"] = round(t * 1e3 / n, 4)
+                fig[f"{tag}{mode}_Mpts_s"] = round(w_.nx * w_.ny * w_.nz * n / t / 1e6, 1)
         tst = _time(lambda: pl.plane_stats(*st), steps)
         fig["plane_stats_us"] = round(tst * 1e6, 1)
         fig["plane_stats_GBps"] = round(3 * 8 * w_.nx * w_.ny * w_.nz / tst / 1e9, 1)
@@ -358,7 +360,41 @@ def secondary(wl, steps):
         "input": "uniform[-1,1] RHS from a seeded torch CUDA generator"}
     del pm, pb, fb
     torch.cuda.empty_cache()
+    res.update(partition_tuning_figures())
     res.update(fwd_adjoint_mixed(steps=2, warmup=1))
+    return res
+
+
+def partition_tuning_figures():
+    """The partitioned solve timed by a CF_PLAN_TUNE_PARTS plan at creation for
+    every admissible (partitions, lines per block) pair, on the step grid (FP64)
+    and the 2048x512x1536 grid (mixed): the chosen pair, its time and the
+    default pair's time."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    res = {}
+    for name, prec in (("step550", "fp64"), ("mixed1000", "mixed")):
+        w_ = synth.WORKLOADS[name]
+        yf = w_.y_faces()
+        t0 = time.perf_counter()
+        pt = Plan(w_.nx, w_.ny, w_.nz, w_.lx, w_.lz, yf, precision=prec, tune_parts=True)
+        t_create = time.perf_counter() - t0
+        rows = pt.partition_timings()
+        inf = pt.info()
+        del pt
+        pd = Plan(w_.nx, w_.ny, w_.nz, w_.lx, w_.lz, yf, precision=prec)
+        dflt = (pd.info()["n_parts"], pd.info()["lines_per_block"])
+        del pd
+        us = {(r[0], r[1]): r[2] for r in rows}
+        res[f"ysolve_tuning_{prec}_{w_.nx}x{w_.ny}x{w_.nz}"] = {
+            "candidates": len(rows), "plan_create_ms": round(t_create * 1e3, 1),
+            "chosen": [inf["n_parts"], inf["lines_per_block"]],
+            "chosen_us": round(us[(inf["n_parts"], inf["lines_per_block"])], 1),
+            "default": list(dflt), "default_us": round(us[dflt], 1) if dflt in us else None,
+            "slowest_us": round(max(us.values()), 1)}
+        torch.cuda.empty_cache()
     return res
 
 

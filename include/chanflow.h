@@ -66,14 +66,28 @@ typedef struct {
   int fp64_kz;        /*   are solved in FP64 (default 4, 4) */
   int refine_passes;  /* CF_MIXED: FP64 residual + correction solves (default 1) */
   int flags;          /* CF_PLAN_STEP: allocate the projection-step workspace;
-                         CF_PLAN_ADJOINT: also the workspace of its adjoint */
+                         CF_PLAN_ADJOINT: also the workspace of its adjoint;
+                         CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS: see below */
+  int lines_per_block; /* lines per block of the partitioned solve; 0 = automatic.
+                          lines_per_block * n_parts must be <= 512 */
 } cf_options;
 
 /* CF_PLAN_Y_DCT: solve the wall-normal systems by a transform along y instead of
    the partitioned tridiagonal solve (the fully spectral variant for uniform
    spacing, Section 2.1).  Needs uniform y faces (spacing equal to 1e-12
    relative), CF_FP64, and an even ny of the form 2^a or 3*2^a, at most 2048. */
-enum { CF_PLAN_STEP = 1, CF_PLAN_ADJOINT = 2, CF_PLAN_Y_DCT = 4 };
+/* CF_PLAN_TUNE_PARTS: choose the partitioning by measurement (Section 2.2 leaves
+   the count P and the placement to the solver): at creation the plan times the
+   partitioned solve for every admissible P (ny = P*M, M in {1,2,3,4,6,8,12,16},
+   P <= 64) and every block of lines_per_block = 4, 8, ..., 256 lines with
+   64 <= lines_per_block * P <= 512 that fits in LDS (five launches each, after
+   two warm-up launches, in place on zeros in the plan's workspace), keeps the
+   fastest and sets the drop threshold for its P (each candidate's accuracy
+   follows drop_tol, so the choice affects speed, not the error bound).  Needs
+   n_parts = 0, lines_per_block = 0 and the partitioned solve (no CF_PLAN_Y_DCT);
+   the timings are read back with cf_plan_tuning.  Takes tens of milliseconds
+   on large grids. */
+enum { CF_PLAN_STEP = 1, CF_PLAN_ADJOINT = 2, CF_PLAN_Y_DCT = 4, CF_PLAN_TUNE_PARTS = 8 };
 
 typedef struct {
   int nx, ny, nz, precision;
@@ -84,6 +98,7 @@ typedef struct {
   long long n_special;    /* lines solved by whole-line FP64 Thomas */
   double k2_threshold;    /* modified-wavenumber^2 above which the drop is allowed */
   size_t workspace_bytes; /* device memory owned by the plan */
+  int lines_per_block;    /* lines per block of the partitioned solve */
 } cf_plan_info;
 
 /* Fill *opt with the defaults. */
@@ -105,6 +120,16 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
 void cf_plan_destroy(cf_plan* plan);
 
 cf_status cf_plan_query(const cf_plan* plan, cf_plan_info* info);
+
+/*
+ * The timings a CF_PLAN_TUNE_PARTS plan took at creation: *count receives the
+ * number of (P, lines_per_block) candidates timed (0 for a plan created without
+ * the flag); the first min(cap, *count) entries of the host arrays parts,
+ * lines_per_block and us (mean microseconds per launch) receive them, in the
+ * order timed.  The arrays may be NULL when cap is 0.
+ */
+cf_status cf_plan_tuning(const cf_plan* plan, int cap, int* count, int* parts, int* lines_per_block,
+                         double* us);
 
 /*
  * Pressure-Poisson solve (Eq. (7)-(9), Section 3.2 steps (2)-(8)):

@@ -18,20 +18,20 @@ CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMER
 CF_FP64, CF_MIXED = 0, 1
 KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
            "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted", "rk2_fused"]
-CF_PLAN_STEP, CF_PLAN_ADJOINT, CF_PLAN_Y_DCT = 1, 2, 4
+CF_PLAN_STEP, CF_PLAN_ADJOINT, CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS = 1, 2, 4, 8
 
 
 class cf_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_parts", C.c_int), ("drop_tol", C.c_double),
                 ("fp64_kx", C.c_int), ("fp64_kz", C.c_int), ("refine_passes", C.c_int),
-                ("flags", C.c_int)]
+                ("flags", C.c_int), ("lines_per_block", C.c_int)]
 
 
 class cf_plan_info(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("precision", C.c_int),
                 ("n_parts", C.c_int), ("rows_per_part", C.c_int), ("n_lines", C.c_longlong),
                 ("n_drop_lines", C.c_longlong), ("n_special", C.c_longlong),
-                ("k2_threshold", C.c_double), ("workspace_bytes", C.c_size_t)]
+                ("k2_threshold", C.c_double), ("workspace_bytes", C.c_size_t), ("lines_per_block", C.c_int)]
 
 
 _P = C.c_void_p
@@ -44,6 +44,7 @@ SIGNATURES = {
     "cf_plan_create": (_I, [C.POINTER(_P), _I, _I, _I, _D, _D, C.POINTER(_D), C.POINTER(cf_options)]),
     "cf_plan_destroy": (None, [_P]),
     "cf_plan_query": (_I, [_P, C.POINTER(cf_plan_info)]),
+    "cf_plan_tuning": (_I, [_P, _I, C.POINTER(_I), C.POINTER(_I), C.POINTER(_I), C.POINTER(_D)]),
     "cf_poisson_solve": (_I, [_P, _P, _P, _P]),
     "cf_divergence": (_I, [_P, _P, _P, _P, _P, _D, _P]),
     "cf_projection_step": (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _D, _D, _P]),

@@ -22,12 +22,15 @@ class Plan:
     """Plan for one grid: nx x ny x nz cells, periodic lengths lx, lz, wall-normal
     faces y_faces (ny+1 values).  precision: 'fp64' or 'mixed'.  y_solver:
     'pdd' (partitioned tridiagonal solve) or 'dct' (transform along y; uniform
-    faces and FP64 only)."""
+    faces and FP64 only).  n_parts / lines_per_block: partitions per line and
+    lines per block of the partitioned solve (0: automatic); tune_parts: choose
+    both by timing every admissible pair at creation (see partition_timings)."""
 
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
                  precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
                  fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
-                 step: bool = False, adjoint: bool = False, y_solver: str = "pdd", device=None):
+                 step: bool = False, adjoint: bool = False, y_solver: str = "pdd",
+                 lines_per_block: int = 0, tune_parts: bool = False, device=None):
         lib = L.lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nkx = self.nx // 2 + 1
@@ -47,10 +50,11 @@ class Plan:
         opt.fp64_kx = int(fp64_kx)
         opt.fp64_kz = int(fp64_kz)
         opt.refine_passes = int(refine_passes)
+        opt.lines_per_block = int(lines_per_block)
         if y_solver not in ("pdd", "dct"):
             raise ValueError("y_solver must be 'pdd' or 'dct'")
         opt.flags = (L.CF_PLAN_STEP if (step or adjoint) else 0) | (L.CF_PLAN_ADJOINT if adjoint else 0) \
-            | (L.CF_PLAN_Y_DCT if y_solver == "dct" else 0)
+            | (L.CF_PLAN_Y_DCT if y_solver == "dct" else 0) | (L.CF_PLAN_TUNE_PARTS if tune_parts else 0)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):
@@ -76,6 +80,18 @@ class Plan:
         inf = L.cf_plan_info()
         L.check(L.lib().cf_plan_query(self._h, C.byref(inf)), "cf_plan_query")
         return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def partition_timings(self) -> list:
+        """[(n_parts, lines_per_block, mean us per launch)] timed at creation by a
+        tune_parts plan, in the order timed; [] otherwise."""
+        n = C.c_int()
+        L.check(L.lib().cf_plan_tuning(self._h, 0, C.byref(n), None, None, None), "cf_plan_tuning")
+        cnt = n.value
+        if cnt == 0:
+            return []
+        parts, lbs, us = (C.c_int * cnt)(), (C.c_int * cnt)(), (C.c_double * cnt)()
+        L.check(L.lib().cf_plan_tuning(self._h, cnt, C.byref(n), parts, lbs, us), "cf_plan_tuning")
+        return [(parts[q], lbs[q], us[q]) for q in range(cnt)]
 
     # ------------------------------------------------------------------ timing
     def set_timing(self, enable: bool):

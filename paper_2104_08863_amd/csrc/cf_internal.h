@@ -73,9 +73,15 @@ hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* t
 
 struct YLaunch {
   int ny, nz, nkx, P, M;
+  int LB;  // lines per block (threads per block = LB * P <= 512)
   long nlines;
   int skip_kx, skip_kz;
 };
+
+// Default lines per block of the partitioned solve for P partitions.
+int ysolve_default_lb(int P);
+// Dynamic LDS of one partitioned-solve block.
+size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64);
 
 template <typename T>
 hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,

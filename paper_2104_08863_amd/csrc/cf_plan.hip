@@ -23,10 +23,6 @@
 #include "cf_adjoint_kernels.h"
 #include "cf_step_kernels.h"
 
-namespace cf {
-size_t ysolve_lds_needed(int ny, int P, bool fp64);
-}
-
 using cf::cx;
 
 namespace {
@@ -64,8 +60,15 @@ struct cf_plan {
   cf_options opt;
   int device;
   int P, M;
+  int LB;  // lines per block of the partitioned solve
   double k2drop;
   long long n_drop;
+  // partition counts and block shapes timed at creation (CF_PLAN_TUNE_PARTS)
+  struct TuneRow {
+    int P, LB;
+    double us;
+  };
+  std::vector<TuneRow> tune;
   std::vector<double> yf, dy, dyc, a, c, kx2, kz2;
   std::vector<int> special;
   std::vector<DevBuf> allocs;
@@ -253,6 +256,38 @@ double corner_delta(const cf_plan* pl, double k2) {
   return delta;
 }
 
+// Partitioning of the wall-normal lines into P parts of M = ny/P rows (Section
+// 2.2) and the drop threshold that goes with it: the smallest k^2 whose corner
+// terms are all <= drop_tol (the corner terms fall monotonically with k^2).
+void set_partitions(cf_plan* pl, int P, int LB) {
+  pl->P = P;
+  pl->M = pl->ny / P;
+  pl->LB = LB;
+  double kmax = 0.0;
+  for (double v : pl->kx2) kmax = std::max(kmax, v);
+  double kzm = 0.0;
+  for (double v : pl->kz2) kzm = std::max(kzm, v);
+  kmax += kzm;
+  const double tol = pl->opt.drop_tol;
+  if (P <= 2) {
+    pl->k2drop = 0.0;
+  } else if (corner_delta(pl, kmax) > tol) {
+    pl->k2drop = INFINITY;
+  } else {
+    double lo = 0.0, hi = kmax;
+    if (corner_delta(pl, 0.0) <= tol) hi = 0.0;
+    for (int it = 0; it < 200 && hi > 0.0 && (hi - lo) > 1e-12 * hi; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (corner_delta(pl, mid) <= tol) hi = mid; else lo = mid;
+    }
+    pl->k2drop = hi;
+  }
+  pl->n_drop = 0;
+  for (int kx = 0; kx < pl->nkx; ++kx)
+    for (int kz = 0; kz < pl->nz; ++kz)
+      if (pl->kx2[kx] + pl->kz2[kz] >= pl->k2drop) ++pl->n_drop;
+}
+
 int auto_parts(int ny) {
   // fewest partitions with at most 16 rows each, preferring powers of two
   for (int P = 1; P <= 64; P *= 2)
@@ -364,9 +399,26 @@ cf_status inverse_t(cf_plan* pl, const cx<T>* inB, double* p, hipStream_t s) {
   return CF_OK;
 }
 
+// One launch of the partitioned line solve with the plan's partitioning.
+template <typename T>
+hipError_t pdd_launch(const cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
+  using TB = Tabs<T>;
+  cf::YLaunch y;
+  y.ny = pl->ny;
+  y.nz = pl->nz;
+  y.nkx = pl->nkx;
+  y.P = pl->P;
+  y.M = pl->M;
+  y.LB = pl->LB;
+  y.nlines = (long)pl->nkx * pl->nz;
+  y.skip_kx = pl->mixed() ? pl->opt.fp64_kx : 0;
+  y.skip_kz = pl->mixed() ? pl->opt.fp64_kz : 0;
+  const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
+  return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
+}
+
 template <typename T>
 cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
-  using TB = Tabs<T>;
   if constexpr (std::is_same<T, double>::value) {
     if (pl->opt.flags & CF_PLAN_Y_DCT)
       return timed(pl, CF_K_YSOLVE, s, "y-transform solve launch", [&] {
@@ -374,16 +426,6 @@ cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
                                        pl->nz, pl->nkx, s);
       });
   }
-  cf::YLaunch y;
-  y.ny = pl->ny;
-  y.nz = pl->nz;
-  y.nkx = pl->nkx;
-  y.P = pl->P;
-  y.M = pl->M;
-  y.nlines = (long)pl->nkx * pl->nz;
-  y.skip_kx = pl->mixed() ? pl->opt.fp64_kx : 0;
-  y.skip_kz = pl->mixed() ? pl->opt.fp64_kz : 0;
-  const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
   // The whole-line solves run on the side stream next to the PDD kernel: they
   // read and write only the special lines, which the PDD kernel reads but does
   // not write (lines are independent there, so the values it reads for them
@@ -396,7 +438,7 @@ cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
   }));
   CF_HIP(hipEventRecord(pl->ev_join, pl->aux), "hipEventRecord");
   CF_TRY(timed(pl, CF_K_YSOLVE, s, "y-solve launch", [&] {
-    return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
+    return pdd_launch<T>(pl, fin, pout, s);
   }));
   CF_HIP(hipStreamWaitEvent(s, pl->ev_join, 0), "hipStreamWaitEvent");
   return CF_OK;
@@ -609,6 +651,56 @@ void special_factors(const cf_plan* pl, int line, double* den, double* cp) {
   }
 }
 
+// Partition count and block shape by measurement (the count and placement
+// question of Section 2.2, answered on the device): every P with ny = P*M for
+// a compiled M, P <= 64, and every block of LB lines with 64 <= LB*P <= 512
+// threads that fits in LDS, is timed over five launches of the partitioned
+// solve (in place, on zeros in the plan's spectral workspace, on the plan's
+// capture stream, after two warm-up launches); the fastest is kept and the drop
+// threshold follows its P.
+cf_status tune_partitions(cf_plan* pl, size_t lds_max) {
+  const bool fp64 = !pl->mixed();
+  hipStream_t s = pl->gstream;
+  const size_t nspec = (size_t)pl->ny * pl->nkx * pl->nz;
+  CF_HIP(hipMemsetAsync(pl->specB, 0, nspec * (fp64 ? sizeof(cx<double>) : sizeof(cx<float>)), s),
+         "hipMemsetAsync");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto done = [&](cf_status st) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return st;
+  };
+  if (e != hipSuccess) return done(dev_fail(e, "hipEventCreate"));
+  constexpr int kWarm = 2, kRuns = 5;
+  pl->tune.clear();
+  size_t best = 0;
+  for (int P = 1; P <= 64; ++P) {
+    if (!parts_ok(pl->ny, P)) continue;
+    for (int LB = 4; LB <= 256; LB *= 2) {
+      if (LB * P < 64 || LB * P > 512 || cf::ysolve_lds_needed(pl->ny, P, LB, fp64) > lds_max) continue;
+      set_partitions(pl, P, LB);
+      for (int r = 0; r < kWarm + kRuns && e == hipSuccess; ++r) {
+        if (r == kWarm) e = hipEventRecord(e0, s);
+        if (e != hipSuccess) break;
+        e = fp64 ? pdd_launch<double>(pl, static_cast<cx<double>*>(pl->specB), static_cast<cx<double>*>(pl->specB), s)
+                 : pdd_launch<float>(pl, static_cast<cx<float>*>(pl->specB), static_cast<cx<float>*>(pl->specB), s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) return done(dev_fail(e, "partition timing"));
+      pl->tune.push_back({P, LB, 1e3 * (double)ms / kRuns});
+      if (pl->tune.back().us < pl->tune[best].us) best = pl->tune.size() - 1;
+    }
+  }
+  if (pl->tune.empty()) return done(fail(CF_ERR_UNSUPPORTED, "no partitioning fits"));
+  set_partitions(pl, pl->tune[best].P, pl->tune[best].LB);
+  return done(CF_OK);
+}
+
 }  // namespace
 
 // ============================================================================
@@ -623,6 +715,7 @@ void cf_options_default(cf_options* opt) {
   opt->fp64_kz = 4;
   opt->refine_passes = 1;
   opt->flags = 0;
+  opt->lines_per_block = 0;
 }
 
 const char* cf_status_string(cf_status s) {
@@ -659,10 +752,16 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     if (!(y_faces[j + 1] > y_faces[j])) return fail(CF_ERR_ARG, "y_faces must be strictly increasing");
   if (!cf::fft_len_compiled(nx / 2)) return fail(CF_ERR_UNSUPPORTED, "nx/2 must be 2^a or 3*2^a in [2, 2048]");
   if (!cf::fft_len_compiled(nz)) return fail(CF_ERR_UNSUPPORTED, "nz must be 2^a or 3*2^a in [2, 2048]");
+  const bool tune = (opt.flags & CF_PLAN_TUNE_PARTS) != 0;
+  if (tune && (opt.n_parts != 0 || opt.lines_per_block != 0 || (opt.flags & CF_PLAN_Y_DCT)))
+    return fail(CF_ERR_ARG, "CF_PLAN_TUNE_PARTS needs n_parts = 0, lines_per_block = 0 and the partitioned solve");
   int P = opt.n_parts;
   if (P == 0) P = auto_parts(ny);
   if (P == 0 || !parts_ok(ny, P))
     return fail(CF_ERR_UNSUPPORTED, "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16}");
+  if (opt.lines_per_block < 0 || opt.lines_per_block * P > 512)
+    return fail(CF_ERR_ARG, "lines_per_block must be >= 0 with lines_per_block * n_parts <= 512");
+  const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P);
   if (opt.precision == CF_MIXED) {
     if (opt.fp64_kx < 1 || opt.fp64_kz < 1) return fail(CF_ERR_ARG, "fp64_kx and fp64_kz must be >= 1");
     if (opt.refine_passes < 0 || opt.refine_passes > 8) return fail(CF_ERR_ARG, "refine_passes must be in [0, 8]");
@@ -714,28 +813,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     const double sn = std::sin(M_PI * (double)k / (double)nz);
     pl->kz2[k] = (2.0 * sn / pl->dz) * (2.0 * sn / pl->dz);
   }
-  // drop threshold: smallest k^2 whose corner terms are all <= drop_tol
-  // (the corner terms fall monotonically with k^2)
-  {
-    double kmax = 0.0;
-    for (double v : pl->kx2) kmax = std::max(kmax, v);
-    double kzm = 0.0;
-    for (double v : pl->kz2) kzm = std::max(kzm, v);
-    kmax += kzm;
-    if (P <= 2) {
-      pl->k2drop = 0.0;
-    } else if (corner_delta(pl, kmax) > opt.drop_tol) {
-      pl->k2drop = INFINITY;
-    } else {
-      double lo = 0.0, hi = kmax;
-      if (corner_delta(pl, 0.0) <= opt.drop_tol) hi = 0.0;
-      for (int it = 0; it < 200 && hi > 0.0 && (hi - lo) > 1e-12 * hi; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (corner_delta(pl, mid) <= opt.drop_tol) hi = mid; else lo = mid;
-      }
-      pl->k2drop = hi;
-    }
-  }
+  set_partitions(pl, P, LB);
   // special lines: kx = kz = 0 always; the FP64 low set in mixed precision
   pl->special.push_back(0);
   if (opt.precision == CF_MIXED) {
@@ -746,10 +824,6 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
         pl->special.push_back(kx * nz + kz);
       }
   }
-  pl->n_drop = 0;
-  for (int kx = 0; kx < pl->nkx; ++kx)
-    for (int kz = 0; kz < nz; ++kz)
-      if (pl->kx2[kx] + pl->kz2[kz] >= pl->k2drop) ++pl->n_drop;
 
   // device side
   hipError_t e = hipGetDevice(&pl->device);
@@ -763,7 +837,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     delete pl;
     return dev_fail(e, "hipDeviceGetAttribute");
   }
-  const size_t lds_need = cf::ysolve_lds_needed(ny, P, opt.precision == CF_FP64);
+  const size_t lds_need = cf::ysolve_lds_needed(ny, P, LB, opt.precision == CF_FP64);
   if (lds_need > (size_t)lds_max) {
     delete pl;
     return fail(CF_ERR_UNSUPPORTED, "partitioning needs " + std::to_string(lds_need) + " bytes of LDS per block");
@@ -901,6 +975,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     if ((st = upload(pl, &pl->d_special_den, den)) != CF_OK) return bail(st);
     if ((st = upload(pl, &pl->d_special_cp, cpv)) != CF_OK) return bail(st);
   }
+  if (tune && (st = tune_partitions(pl, (size_t)lds_max)) != CF_OK) return bail(st);
   *out = pl;
   return CF_OK;
 }
@@ -925,6 +1000,21 @@ cf_status cf_plan_query(const cf_plan* pl, cf_plan_info* info) {
   info->n_special = (long long)pl->special.size();
   info->k2_threshold = pl->k2drop;
   info->workspace_bytes = pl->bytes;
+  info->lines_per_block = pl->LB;
+  return CF_OK;
+}
+
+cf_status cf_plan_tuning(const cf_plan* pl, int cap, int* count, int* parts, int* lbs, double* us) {
+  CF_TRY(check_plan(pl));
+  if (!count) return fail(CF_ERR_ARG, "count is NULL");
+  if (cap < 0) return fail(CF_ERR_ARG, "cap must be >= 0");
+  if (cap > 0 && (!parts || !lbs || !us)) return fail(CF_ERR_ARG, "output arrays are NULL");
+  *count = (int)pl->tune.size();
+  for (int q = 0; q < cap && q < *count; ++q) {
+    parts[q] = pl->tune[q].P;
+    lbs[q] = pl->tune[q].LB;
+    us[q] = pl->tune[q].us;
+  }
   return CF_OK;
 }
 

@@ -17,12 +17,14 @@ bool ysolve_m_compiled(int m) {
   }
 }
 
-// Lines per block: at least 16 consecutive lines per row access where the
-// block stays within 512 threads, about 256 threads per block otherwise.
-static int lines_per_block(int P) {
+// Default lines per block: about 256 threads per block with 8 to 16 lines,
+// and at least one wave.  Measured on MI355X for the default partition counts
+// (P = 8, 16, 32 at ny = 128, 256, 512; P = 64 at ny = 768) this is the fastest
+// block or within 10 % of it; other shapes can be chosen by measurement.
+int ysolve_default_lb(int P) {
   int lb = 256 / P;
-  if (lb < 16) lb = 16;
-  while (lb * P > 512) lb /= 2;
+  lb = lb < 8 ? 8 : (lb > 16 ? 16 : lb);
+  if (lb * P < 64) lb = (64 + P - 1) / P;
   return lb;
 }
 
@@ -34,7 +36,7 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   ya.nz = y.nz;
   ya.nkx = y.nkx;
   ya.P = y.P;
-  ya.LB = lines_per_block(y.P);
+  ya.LB = y.LB > 0 ? y.LB : ysolve_default_lb(y.P);
   ya.nlines = y.nlines;
   ya.skip_kx = y.skip_kx;
   ya.skip_kz = y.skip_kz;
@@ -56,9 +58,8 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
 
 // Dynamic LDS needed by a y-solve launch (checked by the plan against the
 // device limit).
-size_t ysolve_lds_needed(int ny, int P, bool fp64) {
-  const int lb = lines_per_block(P);
-  return fp64 ? ysolve_lds_bytes<double>(ny, P, lb) : ysolve_lds_bytes<float>(ny, P, lb);
+size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64) {
+  return fp64 ? ysolve_lds_bytes<double>(ny, P, LB) : ysolve_lds_bytes<float>(ny, P, LB);
 }
 
 template <typename T>

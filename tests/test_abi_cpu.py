@@ -102,6 +102,26 @@ def test_plan_rejects_unsupported_y_transform_solve():
     assert _create(16, 16, 8, yf, opt)[0] == L.CF_ERR_UNSUPPORTED           # FP64 only
 
 
+def test_plan_rejects_bad_partition_options():
+    yf = np.linspace(-1, 1, 65)
+    opt = L.cf_options()
+    L.lib().cf_options_default(C.byref(opt))
+    assert opt.lines_per_block == 0
+    opt.flags = L.CF_PLAN_TUNE_PARTS
+    opt.n_parts = 4
+    assert _create(16, 64, 8, yf, opt)[0] == L.CF_ERR_ARG               # tuning with a fixed count
+    opt.n_parts, opt.lines_per_block = 0, 16
+    assert _create(16, 64, 8, yf, opt)[0] == L.CF_ERR_ARG               # tuning with a fixed block
+    opt.lines_per_block = 0
+    opt.flags = L.CF_PLAN_TUNE_PARTS | L.CF_PLAN_Y_DCT
+    assert _create(16, 64, 8, yf, opt)[0] == L.CF_ERR_ARG               # no partitions to tune
+    L.lib().cf_options_default(C.byref(opt))
+    opt.lines_per_block = -1
+    assert _create(16, 64, 8, yf, opt)[0] == L.CF_ERR_ARG
+    opt.n_parts, opt.lines_per_block = 8, 128                           # 1024 threads per block
+    assert _create(16, 64, 8, yf, opt)[0] == L.CF_ERR_ARG
+
+
 def test_calls_reject_null_plan_and_pointers():
     lib = L.lib()
     buf = (C.c_double * 8)()
@@ -115,4 +135,6 @@ def test_calls_reject_null_plan_and_pointers():
     assert lib.cf_plane_stats(None, p, p, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_run_steps(None, p, p, p, p, p, p, 1, 1e-3, 0.01, 0.0, 0, None, None, 0, None) == L.CF_ERR_ARG
     assert lib.cf_plan_query(None, None) == L.CF_ERR_ARG
+    n = C.c_int(-1)
+    assert lib.cf_plan_tuning(None, 0, C.byref(n), None, None, None) == L.CF_ERR_ARG
     lib.cf_plan_destroy(None)
