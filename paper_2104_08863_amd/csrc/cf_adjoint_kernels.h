@@ -202,12 +202,16 @@ struct AdjPtrs {
 // fetched into registers while plane j is computed.  lam is formed only when a
 // plane moves from registers to LDS, and every global load is unconditional
 // (clamped address, masked on the move), so the compiler's waits never cover
-// a load still in flight for a later plane.
+// a load still in flight for a later plane.  Each thread fetches its own cell
+// first (a wave reads aligned x runs), so the A + B term of the ADD output is
+// taken from that fetch (two planes kept in registers) instead of a second
+// load.
 template <typename T, int TX, int TZ, int CY, bool HASB, bool ADD>
 __global__ void __launch_bounds__(TX * TZ)
 k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, TH = TX * TZ;
-  constexpr int PER = (PLANE + TH - 1) / TH;
+  constexpr int NHALO = PLANE - TH;                // 2 SX + 2 TZ ring cells
+  constexpr int PER = 1 + (NHALO + TH - 1) / TH;  // own cell first, then ring cells
   constexpr int NF = HASB ? 9 : 6;  // raw fields fetched per tile value
   __shared__ T sm[6 * 3 * PLANE];
   __shared__ T sy[4 * (CY + 2)];
@@ -228,18 +232,36 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   const int i = i0 + tx, k = k0 + tz;
   const bool mine = (i < nx) && (k < nz);
   const long plane = (long)nx * nz;
-  int toff[PER];
+  // tile cells of this thread: q = 0 its own cell (tz+1, tx+1), q >= 1 the
+  // ring cells (top row, bottom row, left column, right column)
+  int toff[PER], cidx[PER];
   bool tin[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = threadIdx.x + q * TH;
-    const int zz = idx / SX, xx = idx % SX;
+    int zz, xx;
+    if (q == 0) {
+      zz = tz + 1;
+      xx = tx + 1;
+      tin[q] = true;
+    } else {
+      const int h = threadIdx.x + (q - 1) * TH;
+      tin[q] = h < NHALO;
+      if (h < SX) {
+        zz = 0, xx = h;
+      } else if (h < 2 * SX) {
+        zz = SZ - 1, xx = h - SX;
+      } else if (h < 2 * SX + TZ) {
+        zz = 1 + h - 2 * SX, xx = 0;
+      } else {
+        zz = 1 + (h - 2 * SX - TZ) % TZ, xx = SX - 1;
+      }
+    }
     int gi = (i0 + xx - 1) % nx;
     if (gi < 0) gi += nx;
     int gk = (k0 + zz - 1) % nz;
     if (gk < 0) gk += nz;
-    tin[q] = idx < PLANE;
     toff[q] = tin[q] ? gk * nx + gi : 0;
+    cidx[q] = zz * SX + xx;
   }
   T r[NF][PER];
 #define CF_ADJ_FETCH(jj)                                                        \
@@ -255,7 +277,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
     const bool pin_ = (jj) >= 0 && (jj) < ny, vin_ = (jj) >= 0 && (jj) < ny - 1; \
     _Pragma("unroll") for (int q = 0; q < PER; ++q) {                          \
       if (tin[q]) {                                                            \
-        const int idx = sl_ * PLANE + threadIdx.x + q * TH;                    \
+        const int idx = sl_ * PLANE + cidx[q];                                 \
         _Pragma("unroll") for (int f = 0; f < 3; ++f) {                        \
           const bool in_ = (f == 1) ? vin_ : pin_;                             \
           const T lam_ = HASB ? c1 * r[3 + f][q] + c2 * r[(6 + f) % NF][q] : c1 * r[3 + f][q]; \
@@ -264,18 +286,17 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
         }                                                                      \
       }                                                                        \
     }                                                                          \
-  }
-  const long pid = (long)k * nx + i;
-  const long pidc = (long)min(k, nz - 1) * nx + min(i, nx - 1);
-  T pa[3] = {T(0), T(0), T(0)}, pb[3] = {T(0), T(0), T(0)};
-#define CF_ADJ_LOAD_PT(jj)                                                      \
-  if (ADD) {                                                                   \
-    const long o_ = (long)min((jj), ny - 1) * plane + pidc;                    \
-    _Pragma("unroll") for (int f = 0; f < 3; ++f) {                            \
-      pa[f] = src[3 + f][o_];                                                  \
-      if (HASB) pb[f] = src[(6 + f) % NF][o_];                                 \
+    if (ADD) {                                                                 \
+      _Pragma("unroll") for (int f = 0; f < 3; ++f) {                          \
+        const T ps_ = HASB ? r[3 + f][0] + r[(6 + f) % NF][0] : r[3 + f][0];   \
+        if ((jj) & 1) ps1[f] = ps_; else ps0[f] = ps_;                         \
+      }                                                                        \
     }                                                                          \
   }
+  const long pid = (long)k * nx + i;
+  // A (+ B) at the own cell of planes with even / odd index, kept from the
+  // move of the plane into LDS for the ADD output
+  T ps0[3] = {T(0), T(0), T(0)}, ps1[3] = {T(0), T(0), T(0)};
   CF_ADJ_FETCH(j0 - 1)
   CF_ADJ_STORE(j0 - 1)
   CF_ADJ_FETCH(j0)
@@ -291,7 +312,6 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   for (int j = j0; j < j1; ++j) {
     CF_ADJ_STORE(j + 1)
     __syncthreads();
-    CF_ADJ_LOAD_PT(j)
     CF_ADJ_FETCH(j + 2)
     A.sm = ((j + 2) % 3) * PLANE;
     A.s0 = (j % 3) * PLANE;
@@ -302,9 +322,9 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
     have = true;
     T ou = s * o.gu, ov = s * o.gv, ow = s * o.gw;
     if (ADD) {
-      ou += HASB ? pa[0] + pb[0] : pa[0];
-      ov += HASB ? pa[1] + pb[1] : pa[1];
-      ow += HASB ? pa[2] + pb[2] : pa[2];
+      ou += (j & 1) ? ps1[0] : ps0[0];
+      ov += (j & 1) ? ps1[1] : ps0[1];
+      ow += (j & 1) ? ps1[2] : ps0[2];
     }
     if (mine) {
       const long id = (long)j * plane + pid;
@@ -316,7 +336,6 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   }
 #undef CF_ADJ_FETCH
 #undef CF_ADJ_STORE
-#undef CF_ADJ_LOAD_PT
 }
 
 // g* = g - W G phi (weighted correction of the projection transpose);

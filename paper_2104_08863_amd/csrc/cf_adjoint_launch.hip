@@ -4,8 +4,9 @@
 
 namespace cf {
 
-// Tile: 32 x 8 columns, chunks of 64 planes (six LDS fields x three planes).
-constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 64;
+// Tile: 32 x 8 columns, chunks of 32 planes (six LDS fields x three planes;
+// 32-plane chunks measured 2 % faster than 64 and 16 on 1024x256x512 FP64).
+constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 32;
 
 template <typename T>
 hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
