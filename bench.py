@@ -128,10 +128,42 @@ def kernel_bytes(name: str, nx: int, ny: int, nz: int, esize_spec: int, esize_ph
     }[name]
 
 
+def _host_info():
+    """Host cores and CPU model name (from /proc/cpuinfo)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def _oracle_rate(call, npts, min_calls=1, max_calls=3, seconds=5.0, warm=True):
+    """Mpts/s of a CPU oracle call: one warm-up call (if warm), then calls
+    until `seconds` have passed or max_calls were made (at least min_calls)."""
+    if warm:
+        call()
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        call()
+        n += 1
+        if n >= max_calls or (n >= min_calls and time.perf_counter() - t0 > seconds):
+            break
+    dt = (time.perf_counter() - t0) / n
+    return round(npts / dt / 1e6, 2), n
+
+
 def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
     """The oracle (plain torch CPU, FP64) on a bounded sample of the workload:
     the same nx x nz planes and y-grid shape with ny reduced so a few calls fit
-    in the time target; Mpts/s = sample points / wall time per call."""
+    in the time target; Mpts/s = sample points / wall time per call.  Also: the
+    same sample with one thread, the 64^3 Poisson solve and the 256x128x256
+    projection step (whole grids) with all threads, and the host's cores and
+    CPU model."""
     import torch
 
     import oracle as O
@@ -151,19 +183,30 @@ def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
         u, v, w = (torch.tensor(q) for q in synth.perturbed_poiseuille(wl.nx, ny_s, wl.nz, yf, seed=0))
         call = lambda: O.projection_step(u, v, w, box, wl.dt, wl.nu, wl.fx)  # noqa: E731
         what = "projection step (RK2 + torch CPU FFT/Thomas Poisson + correction)"
-    call()  # warm-up
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        call()
-        n += 1
-        if time.perf_counter() - t0 > seconds_target / 4 or n >= 3:
-            break
-    dt = (time.perf_counter() - t0) / n
     npts = wl.nx * ny_s * wl.nz
-    return {"value": round(npts / dt / 1e6, 2), "unit": "Mpts/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle {what} on {wl.nx}x{ny_s}x{wl.nz} (the workload's x-z planes, "
-                      f"ny reduced from {wl.ny}), mean of {n} calls"}
+    value, n = _oracle_rate(call, npts, seconds=seconds_target / 4)
+    out = {"value": value, "unit": "Mpts/s", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle {what} on {wl.nx}x{ny_s}x{wl.nz} (the workload's x-z planes, "
+                     f"ny reduced from {wl.ny}), mean of {n} calls"}
+    try:
+        torch.set_num_threads(1)
+        v1, n1 = _oracle_rate(call, npts, max_calls=1, warm=False)
+    finally:
+        torch.set_num_threads(threads)
+    out["single_thread"] = {"value": v1, "cores": 1, "calls": n1}
+    # whole small grids with all threads
+    w1 = synth.WORKLOADS["poisson64"]
+    b1 = O.Box(w1.nx, w1.ny, w1.nz, w1.lx, w1.lz, w1.y_faces())
+    f1 = torch.tensor(synth.uniform_rhs(w1.nx, w1.ny, w1.nz, seed=0))
+    out["poisson_fp64_64x64x64"], _ = _oracle_rate(lambda: O.poisson(f1, b1), w1.nx * w1.ny * w1.nz)
+    w4 = synth.WORKLOADS["rollout256"]
+    y4 = w4.y_faces()
+    b4 = O.Box(w4.nx, w4.ny, w4.nz, w4.lx, w4.lz, y4)
+    u4, v4, w4f = (torch.tensor(q) for q in synth.perturbed_poiseuille(w4.nx, w4.ny, w4.nz, y4, seed=0))
+    out["step_fp64_256x128x256"], _ = _oracle_rate(
+        lambda: O.projection_step(u4, v4, w4f, b4, w4.dt, w4.nu, w4.fx), w4.nx * w4.ny * w4.nz, max_calls=1)
+    out["host"] = _host_info()
+    return out
 
 
 def _time(fn, steps, warmup=2):
@@ -241,6 +284,28 @@ def rollout_figure(steps):
     return {"rollout_fwd_adjoint_fp64_256x128x256": {
         "grid": [w_.nx, w_.ny, w_.nz], "steps": 8, "checkpoint_every": 2,
         "ms_per_step": round(t * 1e3 / 8, 4), "ms_per_rollout": round(t * 1e3, 3)}}
+
+
+def profile_fwd_adjoint(steps: int):
+    """FP64 forward + adjoint steps on the step grid (the fwd_adjoint_step_fp64
+    figure's inputs), one warm-up step, for a kernel-trace profile."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    wl = synth.WORKLOADS["step550"]
+    yf = wl.y_faces()
+    pa = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64", adjoint=True)
+    u, v, w = (torch.tensor(q, device=dev) for q in synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0))
+    o = tuple(torch.empty_like(u) for _ in range(3))
+    g1 = tuple(torch.tensor(q, device=dev) for q in synth.random_directions(wl.nx, wl.ny, wl.nz, seed=1))
+    go = tuple(torch.empty_like(u) for _ in range(3))
+    for k in range(steps + 1):
+        pa.projection_step(u, v, w, wl.dt, wl.nu, wl.fx, out=o)
+        pa.projection_step_adjoint(u, v, w, *g1, wl.dt, wl.nu, wl.fx, out=go)
+        torch.cuda.synchronize()
+        print(f"fwd+adjoint step {k} done", flush=True)
 
 
 def fwd_adjoint_mixed(steps: int = 2, warmup: int = 1):
@@ -411,6 +476,8 @@ def main():
                     help="time the Poisson solve alone instead of the projection step")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="print the traffic table of rocprofv3 --pmc passes and exit")
     ap.add_argument("--summarize-trace", metavar="CSV", help="print a rocprofv3 kernel_stats.csv as markdown and exit")
+    ap.add_argument("--profile-fwd-adjoint", type=int, default=0, metavar="STEPS",
+                    help="only run STEPS FP64 forward + adjoint steps on the step grid (for a profiler) and exit")
     ap.add_argument("--profile-fwd-adjoint-mixed", action="store_true",
                     help="only run two mixed-precision forward + adjoint steps on 2048x768x2048 (for a "
                          "profiler) and exit")
@@ -426,6 +493,9 @@ def main():
         return
     if args.profile_fwd_adjoint_mixed:
         fwd_adjoint_mixed(steps=2, warmup=0)
+        return
+    if args.profile_fwd_adjoint:
+        profile_fwd_adjoint(args.profile_fwd_adjoint)
         return
     if args.calibrate_copy:
         import torch
