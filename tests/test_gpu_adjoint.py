@@ -115,6 +115,36 @@ def test_rollout_finite_differences_256x128x256():
     print(f"rollout FD check: worst relative error over 16 directions {worst:.2e}")
 
 
+def test_step_adjoint_full_size_finite_differences():
+    """The benchmarked FP64 configuration (1024x256x512, tanh factor 2.5, dt
+    4e-5, nu 1/550): for an adjoint field g1 and three random directions d,
+    <J^T g1, d> from the adjoint step equals the central difference of
+    <g1, S(u + h d)> (h = 1e-4) to 1e-6, S the projection step."""
+    from paper_2104_08863_amd.api import Plan
+    wl = synth.WORKLOADS["step550"]
+    yf = wl.y_faces()
+    pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64", adjoint=True)
+    u = [torch.tensor(q, device=dev()) for q in synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0)]
+    g1 = [torch.tensor(q, device=dev()) for q in synth.random_directions(wl.nx, wl.ny, wl.nz, seed=1)]
+    gu = pl.projection_step_adjoint(*u, *g1, wl.dt, wl.nu, wl.fx)
+    h = 1e-4
+    worst = 0.0
+    for seed in (2, 3, 4):
+        d = [torch.tensor(q, device=dev()) for q in synth.random_directions(wl.nx, wl.ny, wl.nz, seed)]
+        sp = pl.projection_step(*(a + h * e for a, e in zip(u, d)), wl.dt, wl.nu, wl.fx)
+        ip = sum(float((a * b).sum()) for a, b in zip(sp, g1))
+        del sp
+        sm = pl.projection_step(*(a - h * e for a, e in zip(u, d)), wl.dt, wl.nu, wl.fx)
+        im = sum(float((a * b).sum()) for a, b in zip(sm, g1))
+        del sm
+        fd = (ip - im) / (2 * h)
+        an = sum(float((a * e).sum()) for a, e in zip(gu, d))
+        err = abs(fd - an) / max(abs(fd), abs(an))
+        worst = max(worst, err)
+        assert err <= 1e-6, f"direction {seed}: FD {fd:.12e} adjoint {an:.12e} rel {err:.2e}"
+    print(f"full-size step FD check: worst relative error over 3 directions {worst:.2e}")
+
+
 @pytest.mark.parametrize("nx,ny,nz,gamma", [(32, 16, 24, 2.0), (64, 48, 32, 3.0)])
 def test_mixed_step_adjoint_matches_oracle_gradient(nx, ny, nz, gamma):
     """FP32 state, FP32-bulk transposed projection with FP64 low lines and one
