@@ -426,7 +426,48 @@ def secondary(wl, steps):
     del pm, pb, fb
     torch.cuda.empty_cache()
     res.update(partition_tuning_figures())
+    res.update(slab_figures(steps))
     res.update(fwd_adjoint_mixed(steps=2, warmup=1))
+    return res
+
+
+def slab_figures(steps):
+    """The wall-normal solve of the step grid split into 8 y-slabs of 32 rows
+    (cf_solve_spectral_slabs; on eight devices each would run one slab, here
+    they run one after another): mean time of one slab's local pass and of one
+    finishing pass, the interface rows one slab contributes, and the one-pass
+    solve for comparison."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    wl = synth.WORKLOADS["step550"]
+    pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces(), precision="fp64")
+    g = 8
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    fh = torch.randn(pl.nkx, wl.ny, wl.nz, dtype=torch.complex128, device=dev, generator=gen)
+    out = torch.empty_like(fh)
+    iface = torch.empty(pl.info()["slab_iface_bytes"], dtype=torch.uint8, device=dev)
+    t_one = _time(lambda: pl.solve_spectral(fh, out=out), steps)
+    t_all = _time(lambda: pl.solve_spectral_slabs(fh, g, out=out, iface=iface), steps)
+    pl.set_timing(True)
+    pl.reset_timing()
+    for _ in range(steps):
+        pl.solve_spectral_slabs(fh, g, out=out, iface=iface)
+    torch.cuda.synchronize()
+    tm = pl.timings()
+    pl.set_timing(False)
+    info = pl.info()
+    res = {"pdd_8_slabs_fp64_1024x256x512": {
+        "slabs": g, "rows_per_slab": wl.ny // g, "partitions_per_slab": info["n_parts"] // g,
+        "local_us_per_slab": round(1e3 * tm["slab_local"][0] / tm["slab_local"][1], 1),
+        "finish_us_per_slab": round(1e3 * tm["slab_finish"][0] / tm["slab_finish"][1], 1),
+        "iface_MB_per_slab": round(info["slab_iface_bytes"] / g / 1e6, 2),
+        "all_slabs_ms": round(t_all * 1e3, 4), "one_pass_ms": round(t_one * 1e3, 4)}}
+    del pl, fh, out, iface
+    torch.cuda.empty_cache()
     return res
 
 

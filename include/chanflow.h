@@ -99,6 +99,8 @@ typedef struct {
   double k2_threshold;    /* modified-wavenumber^2 above which the drop is allowed */
   size_t workspace_bytes; /* device memory owned by the plan */
   int lines_per_block;    /* lines per block of the partitioned solve */
+  size_t slab_iface_bytes; /* device bytes of the interface buffer of cf_solve_spectral_slabs:
+                              n_parts * 8 * n_lines values of the plan's precision */
 } cf_plan_info;
 
 /* Fill *opt with the defaults. */
@@ -249,6 +251,25 @@ cf_status cf_inverse_spectral(cf_plan* plan, const void* phat, double* p, void* 
 cf_status cf_solve_spectral(cf_plan* plan, const void* fhat, void* phat, void* stream);
 
 /*
+ * The solve of cf_solve_spectral split into y-slabs the way the paper splits it
+ * across processes (Section 2.2 PDD; Section 3: each process owns a range of
+ * partitions and exchanges only interface values).  The ny rows of every line
+ * are cut into n_slabs slabs of n_parts / n_slabs partitions (n_slabs must
+ * divide the plan's n_parts).  For every slab a local pass solves its
+ * partitions and writes their interface rows (x~_1, x~_M, v_1, v_M, w_1, w_M
+ * per partition and line) into iface; then, for every slab, a finishing pass
+ * reads all interface rows, solves the reduced system, redoes the slab's local
+ * solves and writes the slab's corrected rows.  On several devices the slabs
+ * would be the devices and iface the buffer they exchange; here the slabs run
+ * one after another on one device.  The result equals cf_solve_spectral's
+ * bitwise.  iface: device buffer of cf_plan_info.slab_iface_bytes (layout
+ * [n_parts][8][n_lines], plan precision), overwritten.  phat may alias fhat.
+ * Not available with CF_PLAN_Y_DCT (no partitions).
+ */
+cf_status cf_solve_spectral_slabs(cf_plan* plan, int n_slabs, const void* fhat, void* phat, void* iface,
+                                  void* stream);
+
+/*
  * Per-kernel timing with HIP events (measurement support).  While enabled, every
  * kernel launch of the plan is bracketed by two events recorded on the launch
  * stream; cf_plan_get_timing synchronises on them and returns the accumulated
@@ -268,7 +289,9 @@ enum {
   CF_K_ADJ_RHS = 10,  /* transposed momentum right-hand side */
   CF_K_ADJ_CORRECT = 11, /* weighted correction of the transposed projection */
   CF_K_RK_FUSED = 12, /* both RK2 stages in one marching pass (forward step) */
-  CF_K_COUNT = 13
+  CF_K_SLAB_LOCAL = 13,  /* y-slab solve: local partition solves + interface rows */
+  CF_K_SLAB_FINISH = 14, /* y-slab solve: reduced system + correction of one slab */
+  CF_K_COUNT = 15
 };
 cf_status cf_plan_set_timing(cf_plan* plan, int enable);
 cf_status cf_plan_reset_timing(cf_plan* plan);

@@ -17,7 +17,8 @@ HOSTLIB_PATH = os.path.join(PKG, "libchanflow_host.so")
 CF_OK, CF_ERR_ARG, CF_ERR_UNSUPPORTED, CF_ERR_NOMEM, CF_ERR_DEVICE, CF_ERR_NUMERIC = range(6)
 CF_FP64, CF_MIXED = 0, 1
 KERNELS = ["r2c_x", "fft_z_fwd", "ysolve", "special_lines", "fft_z_inv", "c2r_x", "divergence",
-           "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted", "rk2_fused"]
+           "rk_stage1", "rk_stage2", "correct", "rhs_adjoint", "correct_weighted", "rk2_fused",
+           "slab_local", "slab_finish"]
 CF_PLAN_STEP, CF_PLAN_ADJOINT, CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS = 1, 2, 4, 8
 
 
@@ -31,7 +32,8 @@ class cf_plan_info(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("precision", C.c_int),
                 ("n_parts", C.c_int), ("rows_per_part", C.c_int), ("n_lines", C.c_longlong),
                 ("n_drop_lines", C.c_longlong), ("n_special", C.c_longlong),
-                ("k2_threshold", C.c_double), ("workspace_bytes", C.c_size_t), ("lines_per_block", C.c_int)]
+                ("k2_threshold", C.c_double), ("workspace_bytes", C.c_size_t), ("lines_per_block", C.c_int),
+                ("slab_iface_bytes", C.c_size_t)]
 
 
 _P = C.c_void_p
@@ -56,6 +58,7 @@ SIGNATURES = {
     "cf_forward_spectral": (_I, [_P, _P, _P, _P]),
     "cf_inverse_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral": (_I, [_P, _P, _P, _P]),
+    "cf_solve_spectral_slabs": (_I, [_P, _I, _P, _P, _P, _P]),
     "cf_plan_set_timing": (_I, [_P, _I]),
     "cf_plan_reset_timing": (_I, [_P]),
     "cf_plan_get_timing": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_longlong)]),

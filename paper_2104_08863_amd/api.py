@@ -273,3 +273,19 @@ class Plan:
         out = torch.empty_like(fhat) if out is None else self._spec(out, "out")
         L.check(L.lib().cf_solve_spectral(self._h, _ptr(fhat), _ptr(out), _stream()), "cf_solve_spectral")
         return out
+
+    def solve_spectral_slabs(self, fhat: torch.Tensor, n_slabs: int, out=None, iface=None) -> torch.Tensor:
+        """solve_spectral split into n_slabs y-slabs (local passes, interface
+        buffer, finishing passes), as the solve would run across n_slabs
+        devices.  iface: uint8 device buffer of info()['slab_iface_bytes']
+        (allocated when None)."""
+        self._spec(fhat, "fhat")
+        out = torch.empty_like(fhat) if out is None else self._spec(out, "out")
+        need = self.info()["slab_iface_bytes"]
+        if iface is None:
+            iface = torch.empty(need, dtype=torch.uint8, device=self.device)
+        elif iface.device != self.device or iface.numel() * iface.element_size() < need or not iface.is_contiguous():
+            raise ValueError(f"iface must be a contiguous device buffer of at least {need} bytes")
+        L.check(L.lib().cf_solve_spectral_slabs(self._h, int(n_slabs), _ptr(fhat), _ptr(out), _ptr(iface),
+                                                _stream()), "cf_solve_spectral_slabs")
+        return out

@@ -65,4 +65,13 @@ CF_HD float rcp(float x) {
 template <typename T> CF_HD T cf_max(T a, T b) { return a > b ? a : b; }
 template <typename T> CF_HD T cf_min(T a, T b) { return a < b ? a : b; }
 
+// Modes of the partitioned solve.  kWhole: every partition of a line in one
+// block.  The two slab modes split the same computation at the point where a
+// partition needs data from the others (the paper's exchange across
+// processes): kSlabLocal runs the local solves of the partitions [pa, pb) and
+// writes their interface rows; kSlabFinish reads every partition's interface
+// rows, solves the reduced system, redoes the local solves of [pa, pb) and
+// writes their corrected rows.
+enum YMode { kWhole = 0, kSlabLocal = 1, kSlabFinish = 2 };
+
 }  // namespace cf

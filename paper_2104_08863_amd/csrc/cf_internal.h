@@ -76,6 +76,9 @@ struct YLaunch {
   int LB;  // lines per block (threads per block = LB * P <= 512)
   long nlines;
   int skip_kx, skip_kz;
+  int mode = 0;            // YMode: whole lines, or one y-slab's local / finishing pass
+  int pa = 0, pb = 0;      // slab modes: partitions [pa, pb)
+  void* iface = nullptr;   // slab modes: interface rows [P][8][nlines] of the plan's precision
 };
 
 // Default lines per block of the partitioned solve for P partitions.

@@ -399,9 +399,11 @@ cf_status inverse_t(cf_plan* pl, const cx<T>* inB, double* p, hipStream_t s) {
   return CF_OK;
 }
 
-// One launch of the partitioned line solve with the plan's partitioning.
+// One launch of the partitioned line solve with the plan's partitioning (whole
+// lines, or one slab's local or finishing pass over partitions [pa, pb)).
 template <typename T>
-hipError_t pdd_launch(const cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
+hipError_t pdd_launch(const cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s, int mode = cf::kWhole,
+                      int pa = 0, int pb = 0, void* iface = nullptr) {
   using TB = Tabs<T>;
   cf::YLaunch y;
   y.ny = pl->ny;
@@ -413,8 +415,38 @@ hipError_t pdd_launch(const cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStrea
   y.nlines = (long)pl->nkx * pl->nz;
   y.skip_kx = pl->mixed() ? pl->opt.fp64_kx : 0;
   y.skip_kz = pl->mixed() ? pl->opt.fp64_kz : 0;
+  y.mode = mode;
+  y.pa = pa;
+  y.pb = pb;
+  y.iface = iface;
   const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
   return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
+}
+
+// The partitioned solve as n_slabs y-slabs: every slab's local pass, then the
+// whole-line FP64 solves of the special lines on the side stream next to every
+// slab's finishing pass (they touch only the special lines, which the
+// finishing passes do not write).
+template <typename T>
+cf_status slabs_t(cf_plan* pl, int n_slabs, const cx<T>* fin, cx<T>* pout, void* iface, hipStream_t s) {
+  const int per = pl->P / n_slabs;
+  for (int g = 0; g < n_slabs; ++g)
+    CF_TRY(timed(pl, CF_K_SLAB_LOCAL, s, "slab local launch", [&] {
+      return pdd_launch<T>(pl, fin, pout, s, cf::kSlabLocal, g * per, (g + 1) * per, iface);
+    }));
+  CF_HIP(hipEventRecord(pl->ev_fork, s), "hipEventRecord");
+  CF_HIP(hipStreamWaitEvent(pl->aux, pl->ev_fork, 0), "hipStreamWaitEvent");
+  CF_TRY(timed(pl, CF_K_SPECIAL, pl->aux, "special-line launch", [&] {
+    return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_special_den, pl->d_special_cp, pl->d_dy,
+                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, pl->aux);
+  }));
+  CF_HIP(hipEventRecord(pl->ev_join, pl->aux), "hipEventRecord");
+  for (int g = 0; g < n_slabs; ++g)
+    CF_TRY(timed(pl, CF_K_SLAB_FINISH, s, "slab finish launch", [&] {
+      return pdd_launch<T>(pl, fin, pout, s, cf::kSlabFinish, g * per, (g + 1) * per, iface);
+    }));
+  CF_HIP(hipStreamWaitEvent(s, pl->ev_join, 0), "hipStreamWaitEvent");
+  return CF_OK;
 }
 
 template <typename T>
@@ -1001,6 +1033,7 @@ cf_status cf_plan_query(const cf_plan* pl, cf_plan_info* info) {
   info->k2_threshold = pl->k2drop;
   info->workspace_bytes = pl->bytes;
   info->lines_per_block = pl->LB;
+  info->slab_iface_bytes = (size_t)pl->P * 8 * (size_t)pl->nkx * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
   return CF_OK;
 }
 
@@ -1044,6 +1077,21 @@ cf_status cf_solve_spectral(cf_plan* pl, const void* fhat, void* phat, void* str
   if (pl->mixed())
     return solve_t<float>(pl, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), s);
   return solve_t<double>(pl, static_cast<const cx<double>*>(fhat), static_cast<cx<double>*>(phat), s);
+}
+
+cf_status cf_solve_spectral_slabs(cf_plan* pl, int n_slabs, const void* fhat, void* phat, void* iface,
+                                  void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(fhat, "fhat"));
+  CF_TRY(check_ptr(phat, "phat"));
+  CF_TRY(check_ptr(iface, "iface"));
+  if (pl->opt.flags & CF_PLAN_Y_DCT) return fail(CF_ERR_ARG, "the y-transform solve has no partitions");
+  if (n_slabs < 1 || pl->P % n_slabs != 0)
+    return fail(CF_ERR_ARG, "n_slabs must divide the plan's partition count " + std::to_string(pl->P));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (pl->mixed())
+    return slabs_t<float>(pl, n_slabs, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), iface, s);
+  return slabs_t<double>(pl, n_slabs, static_cast<const cx<double>*>(fhat), static_cast<cx<double>*>(phat), iface, s);
 }
 
 cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream) {
@@ -1355,7 +1403,7 @@ const char* cf_kernel_name(int k) {
   static const char* names[CF_K_COUNT] = {"r2c_x",     "fft_z_fwd", "ysolve",      "special_lines",
                                           "fft_z_inv", "c2r_x",     "divergence",  "rk_stage1",
                                           "rk_stage2", "correct",   "rhs_adjoint", "correct_weighted",
-                                          "rk2_fused"};
+                                          "rk2_fused", "slab_local", "slab_finish"};
   return (k >= 0 && k < CF_K_COUNT) ? names[k] : "unknown";
 }
 

@@ -27,6 +27,8 @@ struct YArgs {
   long nlines;  // nkx * nz
   int skip_kx;  // lines with kx < skip_kx and min(kz, nz-kz) < skip_kz are special
   int skip_kz;
+  int pa, pb;   // slab modes: the partitions [pa, pb) of one y-slab
+  void* iface;  // slab modes: interface rows [P][8][nlines] (x1 re/im, xm re/im, v1, vm, w1, wm)
 };
 
 __device__ __forceinline__ bool is_special(int kx, int kz, int nz, int skip_kx, int skip_kz) {
@@ -42,7 +44,7 @@ __host__ __device__ constexpr size_t ysolve_lds_bytes(int ny, int P, int LB) {
   return sizeof(T) * 2 * ny + (sizeof(cx<T>) * 4 + sizeof(T) * 4 + sizeof(zrow<T>)) * size_t(P) * LB;
 }
 
-template <typename T, int M>
+template <typename T, int M, int MODE>
 __global__ void __launch_bounds__(512)
 k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
          const T* __restrict__ ccoef, const T* __restrict__ kx2, const T* __restrict__ kz2, T k2drop,
@@ -66,7 +68,9 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
     sc[j] = ccoef[j];
   }
   const int q = threadIdx.x % LB;
-  const int i = threadIdx.x / LB;
+  // partition of this thread (a local-mode block has threads for [pa, pb) only)
+  const int i = threadIdx.x / LB + (MODE == kSlabLocal ? ya.pa : 0);
+  const bool own = (MODE == kWhole) || (i >= ya.pa && i < ya.pb);
   const long line = (long)blockIdx.x * LB + q;
   const bool ok = line < ya.nlines;
   const int kx = ok ? int(line / ya.nz) : 0;
@@ -79,17 +83,45 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   cx<T> d[M];
   T v[M], w[M];
 #pragma unroll
-  for (int s = 0; s < M; ++s) d[s] = ok ? fin[base + s * rs] : mk(T(0), T(0));
+  for (int s = 0; s < M; ++s) d[s] = (ok && own) ? fin[base + s * rs] : mk(T(0), T(0));
   __syncthreads();  // coefficients staged
-  pdd_local<M, T>(sa + j0, sc + j0, k2, d, v, w);
+  if (own) pdd_local<M, T>(sa + j0, sc + j0, k2, d, v, w);
 
+  T* ifc = static_cast<T*>(ya.iface);
+  const long nl = ya.nlines;
+  if (MODE == kSlabLocal) {
+    if (ok) {
+      T* r = ifc + (long)i * 8 * nl + line;
+      r[0 * nl] = d[0].re;
+      r[1 * nl] = d[0].im;
+      r[2 * nl] = d[M - 1].re;
+      r[3 * nl] = d[M - 1].im;
+      r[4 * nl] = v[0];
+      r[5 * nl] = v[M - 1];
+      r[6 * nl] = w[0];
+      r[7 * nl] = w[M - 1];
+    }
+    return;
+  }
   const int me = i * LB + q;
-  s_x1[me] = d[0];
-  s_xm[me] = d[M - 1];
-  s_v1[me] = v[0];
-  s_vm[me] = v[M - 1];
-  s_w1[me] = w[0];
-  s_wm[me] = w[M - 1];
+  if (MODE == kWhole) {
+    s_x1[me] = d[0];
+    s_xm[me] = d[M - 1];
+    s_v1[me] = v[0];
+    s_vm[me] = v[M - 1];
+    s_w1[me] = w[0];
+    s_wm[me] = w[M - 1];
+  } else {
+    // every partition's rows as the local passes wrote them (bitwise equal to
+    // this thread's own recomputed values for i in [pa, pb))
+    const T* r = ifc + (long)i * 8 * nl + (ok ? line : 0);
+    s_x1[me] = mk(r[0 * nl], r[1 * nl]);
+    s_xm[me] = mk(r[2 * nl], r[3 * nl]);
+    s_v1[me] = r[4 * nl];
+    s_vm[me] = r[5 * nl];
+    s_w1[me] = r[6 * nl];
+    s_wm[me] = r[7 * nl];
+  }
   // drop the corner terms only when every line of the block allows it
   const int all_drop = __syncthreads_and((!ok) || k2 >= k2drop);
   const int Q = P - 1;
@@ -126,7 +158,7 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   const cx<T> y1p = (i > 0) ? s_y1[(i - 1) * LB + q] : mk(T(0), T(0));
   const cx<T> y2m = (i < Q) ? y2 : mk(T(0), T(0));
   pdd_correct<M, T>(d, v, w, y1p, y2m);
-  if (ok && !is_special(kx, kz, ya.nz, ya.skip_kx, ya.skip_kz)) {
+  if (ok && own && !is_special(kx, kz, ya.nz, ya.skip_kx, ya.skip_kz)) {
 #pragma unroll
     for (int s = 0; s < M; ++s) pout[base + s * rs] = d[s];
   }

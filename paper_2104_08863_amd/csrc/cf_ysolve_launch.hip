@@ -40,20 +40,40 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   ya.nlines = y.nlines;
   ya.skip_kx = y.skip_kx;
   ya.skip_kz = y.skip_kz;
+  ya.pa = y.mode == kWhole ? 0 : y.pa;
+  ya.pb = y.mode == kWhole ? y.P : y.pb;
+  ya.iface = y.iface;
+  if (y.mode != kWhole && (ya.pa < 0 || ya.pb > y.P || ya.pa >= ya.pb || y.iface == nullptr))
+    return hipErrorInvalidValue;
+  // A local-mode block holds the threads of its slab's partitions only and no
+  // interface data, so it takes more lines (about 256 threads) and only the
+  // coefficient rows in LDS.
+  if (y.mode == kSlabLocal) {
+    const int np = ya.pb - ya.pa;
+    while (2 * ya.LB * np <= 256) ya.LB *= 2;
+  }
   const long blocks = (y.nlines + ya.LB - 1) / ya.LB;
-  const size_t lds = ysolve_lds_bytes<T>(y.ny, y.P, ya.LB);
-  const dim3 threads(ya.LB * y.P);
+  const size_t lds = y.mode == kSlabLocal ? sizeof(T) * 2 * (size_t)y.ny : ysolve_lds_bytes<T>(y.ny, y.P, ya.LB);
+  const dim3 threads(ya.LB * (y.mode == kSlabLocal ? ya.pb - ya.pa : y.P));
+#define CF_LAUNCH(M, MODE)                                                                        \
+  hipLaunchKernelGGL((k_ysolve<T, M, MODE>), dim3(blocks), threads, lds, s, fin, pout, a, c, kx2, kz2, \
+                     k2drop, ya)
   switch (y.M) {
-#define CF_CASE(M)                                                                                   \
-  case M:                                                                                           \
-    hipLaunchKernelGGL((k_ysolve<T, M>), dim3(blocks), threads, lds, s, fin, pout, a, c, kx2, kz2, \
-                       k2drop, ya);                                                                 \
+#define CF_CASE(M)                 \
+  case M:                          \
+    if (y.mode == kSlabLocal)      \
+      CF_LAUNCH(M, kSlabLocal);    \
+    else if (y.mode == kSlabFinish) \
+      CF_LAUNCH(M, kSlabFinish);   \
+    else                           \
+      CF_LAUNCH(M, kWhole);        \
     return hipGetLastError();
     CF_FOR_EACH_M(CF_CASE)
 #undef CF_CASE
     default:
       return hipErrorInvalidValue;
   }
+#undef CF_LAUNCH
 }
 
 // Dynamic LDS needed by a y-solve launch (checked by the plan against the

@@ -128,6 +128,7 @@ def test_calls_reject_null_plan_and_pointers():
     p = C.cast(buf, C.c_void_p)
     assert lib.cf_poisson_solve(None, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_solve_spectral(None, p, p, None) == L.CF_ERR_ARG
+    assert lib.cf_solve_spectral_slabs(None, 1, p, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_forward_spectral(None, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_inverse_spectral(None, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_divergence(None, p, p, p, p, 1.0, None) == L.CF_ERR_ARG

@@ -1,0 +1,94 @@
+"""The wall-normal solve split into y-slabs (cf_solve_spectral_slabs): every
+slab's local pass writes its partitions' interface rows, every slab's
+finishing pass solves the reduced system from all of them.  The result must
+equal the one-pass solve bitwise, for every slab count that divides the
+partition count, in FP64 and mixed precision, in place, and at the benchmarked
+grid with eight slabs (one slab per device of an eight-device split)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2104_08863_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def make(nx, ny, nz, gamma, **kw):
+    from paper_2104_08863_amd.api import Plan
+    yf = synth.tanh_faces(ny, gamma)
+    return Plan(nx, ny, nz, 2 * np.pi, np.pi, yf, **kw), O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+
+
+def spectrum(pl, seed, dtype):
+    rng = np.random.default_rng(seed)
+    shape = (pl.nkx, pl.ny, pl.nz)
+    fh = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    fh[0, :, 0].imag = 0.0
+    return torch.tensor(fh, dtype=dtype, device=dev())
+
+
+# (nx, ny, nz, gamma, n_parts): ragged line counts, radix-3 partition counts
+CASES = [(64, 64, 64, 2.0, 4), (128, 128, 96, 2.0, 8), (96, 36, 24, 2.5, 3), (256, 96, 48, 2.5, 6),
+         (48, 24, 12, 2.0, 2)]
+
+
+@pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
+def test_slabs_equal_one_pass_fp64(nx, ny, nz, gamma, parts):
+    pl, box = make(nx, ny, nz, gamma, n_parts=parts)
+    fh = spectrum(pl, 1, torch.complex128)
+    ref = pl.solve_spectral(fh)
+    for g in [d for d in range(1, parts + 1) if parts % d == 0]:
+        got = pl.solve_spectral_slabs(fh, g)
+        assert torch.equal(got, ref), f"{g} slabs"
+    # in place
+    work = fh.clone()
+    pl.solve_spectral_slabs(work, parts, out=work)
+    assert torch.equal(work, ref)
+    # and the oracle (per line, as the one-pass solve is checked)
+    want = O.solve_spectral(fh.cpu().permute(1, 2, 0), box).permute(2, 0, 1).numpy()
+    got = ref.cpu().numpy()
+    err = np.abs(got - want).max(axis=1) / np.abs(want).max(axis=1)
+    assert err.max() <= 1e-11
+
+
+def test_slabs_equal_one_pass_mixed():
+    pl, _ = make(128, 192, 96, 2.0, precision="mixed")
+    assert pl.info()["n_parts"] % 4 == 0
+    fh = spectrum(pl, 2, torch.complex64)
+    ref = pl.solve_spectral(fh)
+    for g in (2, 4):
+        assert torch.equal(pl.solve_spectral_slabs(fh, g), ref), f"{g} slabs"
+
+
+def test_slabs_on_the_benchmarked_grid():
+    """1024x256x512 (tanh factor 2.5, 16 partitions of 16 rows): eight slabs of
+    32 rows, the share of one device of eight."""
+    wl = synth.WORKLOADS["step550"]
+    from paper_2104_08863_amd.api import Plan
+    pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces())
+    assert pl.info()["n_parts"] == 16
+    fh = spectrum(pl, 3, torch.complex128)
+    ref = pl.solve_spectral(fh)
+    got = pl.solve_spectral_slabs(fh, 8)
+    assert torch.equal(got, ref)
+
+
+def test_slabs_reject_bad_arguments():
+    from paper_2104_08863_amd._lib import ChanflowError
+    pl, _ = make(64, 64, 32, 2.0, n_parts=4)
+    fh = spectrum(pl, 4, torch.complex128)
+    with pytest.raises(ChanflowError):
+        pl.solve_spectral_slabs(fh, 3)            # 3 does not divide 4
+    with pytest.raises(ChanflowError):
+        pl.solve_spectral_slabs(fh, 0)
+    with pytest.raises(ValueError):
+        pl.solve_spectral_slabs(fh, 2, iface=torch.empty(16, dtype=torch.uint8, device=dev()))
+    from paper_2104_08863_amd.api import Plan
+    pd = Plan(64, 64, 32, 2 * np.pi, np.pi, np.linspace(-1, 1, 65), y_solver="dct")
+    with pytest.raises(ChanflowError):
+        pd.solve_spectral_slabs(spectrum(pd, 5, torch.complex128), 1)
