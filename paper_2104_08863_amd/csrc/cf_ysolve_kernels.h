@@ -10,7 +10,9 @@
 // LDS; the reduced system is either the dropped 2x2 form (all lines of the
 // block above the plan's k^2 threshold) or the exact block system solved by
 // cyclic reduction.  Lines flagged special (the kx = kz = 0 line, and in mixed
-// precision the lowest-wavenumber set) are not written here.
+// precision the lowest-wavenumber set) are not written here.  The slab modes
+// (YMode) split this kernel at the interface exchange: the interface rows go
+// through a global buffer instead of LDS.
 //
 // k_special_lines: FP64 Thomas along whole lines, one thread per line, with
 // the gauge handling of the singular kx = kz = 0 line.
