@@ -145,6 +145,32 @@ def powerlaw_velocity(nx: int, ny: int, nz: int, seed: int = 0,
     return tuple(out)
 
 
+def powerlaw_velocity_device(nx: int, ny: int, nz: int, seed: int = 0, device="cuda",
+                             exponent: float = -4.0 / 3.0):
+    """The recipe of powerlaw_velocity generated on a device with a seeded
+    torch generator (for grids too large to synthesise on the host): amplitude
+    max(k, 1)^exponent in (kx, kz), uniform random phases, white in y,
+    independent per component, unit RMS, top-wall v zero.  Same distribution,
+    different random stream from the numpy version."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    kx = torch.arange(nx // 2 + 1, dtype=torch.float64, device=device)
+    kz = torch.fft.fftfreq(nz, d=1.0 / nz, dtype=torch.float64, device=device)
+    amp = torch.clamp(torch.sqrt(kx[None, :] ** 2 + kz[:, None] ** 2), min=1.0) ** exponent
+    out = []
+    for _ in range(3):
+        ph = torch.rand(ny, nz, nx // 2 + 1, dtype=torch.float64, device=device, generator=gen) * (2.0 * np.pi)
+        spec = torch.polar(amp.expand(ny, nz, nx // 2 + 1), ph)
+        del ph
+        f = torch.fft.irfft2(spec, s=(nz, nx), dim=(1, 2))
+        del spec
+        f /= torch.sqrt(torch.mean(f * f))
+        out.append(f)
+    out[1][ny - 1] = 0.0
+    return tuple(out)
+
+
 def random_directions(nx: int, ny: int, nz: int, seed: int):
     """N(0,1) perturbation of every free velocity unknown (top-wall v zero)."""
     rng = np.random.default_rng(seed)
