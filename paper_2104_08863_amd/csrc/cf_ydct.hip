@@ -24,11 +24,13 @@ namespace cf {
 
 template <typename T, int N>
 struct YdctCfg {
-  // lines per block: enough threads per block, LDS within 72 KB
+  // lines per block: about 64 threads' worth of lines, 8 to 64 (8 measured
+  // fastest of 4, 8, 16 for N = 128, 256 in FP64: more blocks per CU), fewer
+  // where LDS would exceed 72 KB
   static constexpr int pick(int l) {
     return (l > 1 && (l * lpad_len(N) * int(sizeof(cx<T>)) > 73728 || l * FftT<N>::TPL > 1024)) ? pick(l / 2) : l;
   }
-  static constexpr int want = (256 / FftT<N>::TPL < 16) ? 16 : (256 / FftT<N>::TPL > 64 ? 64 : 256 / FftT<N>::TPL);
+  static constexpr int want = (64 / FftT<N>::TPL < 8) ? 8 : (64 / FftT<N>::TPL > 64 ? 64 : 64 / FftT<N>::TPL);
   static constexpr int LB = pick(want);
   static constexpr int THREADS = LB * FftT<N>::TPL;
 };
@@ -55,9 +57,20 @@ k_ydct(const cx<T>* fin, cx<T>* pout, const cx<T>* __restrict__ tw, const cx<T>*
   const int kx = blockIdx.x / nzb;
   const int kz0 = (blockIdx.x % nzb) * LB;
   const long base = (long)kx * N * nz + kz0;
-  for (int idx = threadIdx.x; idx < N * LB; idx += TH) {
-    const int q = idx % LB, j = idx / LB;
-    lds[q * S + lpad(mk_pos<N>(j))] = (kz0 + q < nz) ? fin[base + (long)j * nz + q] : mk(T(0), T(0));
+  {
+    // all loads of the thread in flight before the first LDS store
+    constexpr int PT = N * LB / TH;
+    cx<T> ld[PT];
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int idx = threadIdx.x + r * TH, q = idx % LB, j = idx / LB;
+      ld[r] = (kz0 + q < nz) ? fin[base + (long)j * nz + q] : mk(T(0), T(0));
+    }
+#pragma unroll
+    for (int r = 0; r < PT; ++r) {
+      const int idx = threadIdx.x + r * TH, q = idx % LB, j = idx / LB;
+      lds[q * S + lpad(mk_pos<N>(j))] = ld[r];
+    }
   }
   __syncthreads();
   const int tl = threadIdx.x % F::TPL, qq = threadIdx.x / F::TPL;
@@ -132,6 +145,7 @@ k_ydct(const cx<T>* fin, cx<T>* pout, const cx<T>* __restrict__ tw, const cx<T>*
     }
   }
   __syncthreads();
+#pragma unroll 4
   for (int idx = threadIdx.x; idx < N * LB; idx += TH) {
     const int q = idx % LB, j = idx / LB;
     if (kz0 + q < nz) pout[base + (long)j * nz + q] = lds[q * S + lpad(j)];
