@@ -197,8 +197,10 @@ cf_status cf_plane_stats(cf_plan* plan, const void* u, const void* v, const void
  * shape and precision, not overlapping the first), so every step writes
  * separate arrays and takes the fused RK2 pass; the newest state ends in
  * (u, v, w) when nsteps is even and in (u2, v2, w2) when it is odd.  After every
- * stats_every-th step (0: never) the plane statistics of the new state (as in
- * cf_plane_stats) are added into stats_acc (device double (ny, 6)); the caller
+ * stats_every-th step (0: never) the plane statistics of the new state (the
+ * quantities of cf_plane_stats, summed by the step's correction pass itself in
+ * a fixed chunk order, so equal to cf_plane_stats up to rounding) are added into
+ * stats_acc (device double (ny, 6)); the caller
  * clears it and divides by the number of samples.  p: optional device double
  * (ny, nz, nx) receiving the last step's pressure, or NULL.
  * use_graph != 0 replays the steps from HIP graphs on a plan-owned stream

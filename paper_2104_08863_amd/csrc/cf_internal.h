@@ -118,6 +118,13 @@ hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T*
 template <typename T>
 hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, const Geo<T>& g, int accumulate,
                               hipStream_t s);
+// The correction of launch_correct fused with the plane statistics of the
+// corrected fields into st (ny, 6) (or added to it); part: scratch of
+// ny * nch * 6 doubles, nch = correct_stats_chunks(nx, ny, nz).
+int correct_stats_chunks(int nx, int ny, int nz);
+template <typename T>
+hipError_t launch_correct_stats(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, double* part, int nch,
+                                double* st, int accumulate, hipStream_t s);
 // Uniform-y wall-normal solve by a DCT-II / DCT-III pair along y (N-point
 // FFTs, N = ny even); in place allowed.  tw: FFT twiddles of length ny;
 // wq: exp(-i pi m / 2ny), m < ny; lam: -(2 sin(pi m / 2ny) / dy)^2, m <= ny.

@@ -96,6 +96,9 @@ struct cf_plan {
   // projection-step workspace: RK stage-1 fields (state precision) and pressure
   void *ub = nullptr, *vb = nullptr, *wb = nullptr;
   double* pws = nullptr;
+  // step plans: per-chunk sums of the fused correction + plane statistics
+  double* d_stat_part = nullptr;
+  int stat_nch = 1;
   double* fws = nullptr;  // mixed precision: copy of f when p aliases it
   // adjoint workspace: projected gradient g* and gb (state precision)
   void *gsu = nullptr, *gsv = nullptr, *gsw = nullptr, *gbu = nullptr, *gbv = nullptr, *gbw = nullptr;
@@ -577,21 +580,24 @@ cf_status rk2_t(cf_plan* pl, const T* u, const T* v, const T* w, T* u1, T* v1, T
 }
 
 // One mixed-precision projection step (FP32 velocity state, FP64 pressure).
+// acc (optional): the plane statistics of the new state are added into it by
+// the correction pass.
 cf_status step_mixed(cf_plan* pl, const float* u, const float* v, const float* w, float* u1, float* v1,
-                     float* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
+                     float* w1, double* p, double dt, double nu, double fx, hipStream_t s, double* acc = nullptr) {
   double* pp = p ? p : pl->pws;
   const float fdt = float(dt), fnu = float(nu), ffx = float(fx);
   CF_TRY(rk2_t<float>(pl, u, v, w, u1, v1, w1, pl->g32, fdt, fnu, ffx, s));
   CF_TRY(poisson_mixed(pl, MixedRhs{1, nullptr, u1, v1, w1, 1.0 / dt}, pp, s));
   CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
-    return cf::launch_correct<float>(u1, v1, w1, pp, pl->g32, fdt, s);
+    return acc ? cf::launch_correct_stats<float>(u1, v1, w1, pp, pl->g32, fdt, pl->d_stat_part, pl->stat_nch, acc, 1, s)
+               : cf::launch_correct<float>(u1, v1, w1, pp, pl->g32, fdt, s);
   }));
   return CF_OK;
 }
 
 // One FP64 projection step.
 cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w, double* u1, double* v1,
-                 double* w1, double* p, double dt, double nu, double fx, hipStream_t s) {
+                 double* w1, double* p, double dt, double nu, double fx, hipStream_t s, double* acc = nullptr) {
   double* pp = p ? p : pl->pws;
   CF_TRY(rk2_t<double>(pl, u, v, w, u1, v1, w1, pl->g64, dt, nu, fx, s));
   cx<double>* B = static_cast<cx<double>*>(pl->specB);
@@ -599,7 +605,8 @@ cf_status step64(cf_plan* pl, const double* u, const double* v, const double* w,
   CF_TRY(solve_t<double>(pl, B, B, s));
   CF_TRY(inverse_t<double>(pl, B, pp, s));
   CF_TRY(timed(pl, CF_K_CORRECT, s, "correction", [&] {
-    return cf::launch_correct<double>(u1, v1, w1, pp, pl->g64, dt, s);
+    return acc ? cf::launch_correct_stats<double>(u1, v1, w1, pp, pl->g64, dt, pl->d_stat_part, pl->stat_nch, acc, 1, s)
+               : cf::launch_correct<double>(u1, v1, w1, pp, pl->g64, dt, s);
   }));
   return CF_OK;
 }
@@ -989,6 +996,8 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
       if ((st = dalloc(pl, &pl->pws, npts)) != CF_OK) return bail(st);
     }
     pl->fws = pl->pws;
+    pl->stat_nch = cf::correct_stats_chunks(nx, ny, nz);
+    if ((st = dalloc(pl, &pl->d_stat_part, (size_t)ny * pl->stat_nch * 6)) != CF_OK) return bail(st);
   } else {
     unsigned char *a = nullptr, *b = nullptr;
     if ((st = dalloc(pl, &a, spec_b)) != CF_OK) return bail(st);
@@ -1175,31 +1184,17 @@ cf_status cf_plane_stats(cf_plan* pl, const void* u, const void* v, const void* 
 
 namespace {
 
-// One step of the time loop from state a to state b (never the same arrays),
-// then, if wanted, the plane statistics of b added into acc.
+// One step of the time loop from state a to state b (never the same arrays);
+// with acc, the correction pass also adds the plane statistics of b into acc.
 cf_status loop_step(cf_plan* pl, void* const a[3], void* const b[3], double* p, double dt, double nu, double fx,
                     double* acc, hipStream_t s) {
-  if (pl->mixed()) {
-    CF_TRY(step_mixed(pl, static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
+  if (pl->mixed())
+    return step_mixed(pl, static_cast<const float*>(a[0]), static_cast<const float*>(a[1]),
                       static_cast<const float*>(a[2]), static_cast<float*>(b[0]), static_cast<float*>(b[1]),
-                      static_cast<float*>(b[2]), p, dt, nu, fx, s));
-    if (acc) {
-      const hipError_t e = cf::launch_plane_stats<float>(static_cast<const float*>(b[0]), static_cast<const float*>(b[1]),
-                                                         static_cast<const float*>(b[2]), acc, pl->g32, 1, s);
-      if (e != hipSuccess) return dev_fail(e, "plane statistics launch");
-    }
-    return CF_OK;
-  }
-  CF_TRY(step64(pl, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
+                      static_cast<float*>(b[2]), p, dt, nu, fx, s, acc);
+  return step64(pl, static_cast<const double*>(a[0]), static_cast<const double*>(a[1]),
                 static_cast<const double*>(a[2]), static_cast<double*>(b[0]), static_cast<double*>(b[1]),
-                static_cast<double*>(b[2]), p, dt, nu, fx, s));
-  if (acc) {
-    const hipError_t e = cf::launch_plane_stats<double>(static_cast<const double*>(b[0]),
-                                                        static_cast<const double*>(b[1]),
-                                                        static_cast<const double*>(b[2]), acc, pl->g64, 1, s);
-    if (e != hipSuccess) return dev_fail(e, "plane statistics launch");
-  }
-  return CF_OK;
+                static_cast<double*>(b[2]), p, dt, nu, fx, s, acc);
 }
 
 // Records loop_step into an executable graph on the plan's capture stream.

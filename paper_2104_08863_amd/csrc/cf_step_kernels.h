@@ -286,6 +286,30 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
 #undef CF_RK_STORE
 }
 
+// u1 = us - dt G p at point id = (j, k, i) (in place); the top-wall v plane is
+// 0.  Returns the corrected values.
+template <typename T>
+__device__ __forceinline__ void correct_point(T* u, T* v, T* w, const double* __restrict__ p, const Geo<T>& g,
+                                              T dt, long id, int i, int k, int j, T& cu, T& cv, T& cw) {
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const long row = id - i;
+  const double p0 = p[id];
+  const T gx = T(p[row + ip] - p0) * g.rdx;
+  const T gz = T(p[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz;
+  cu = u[id] - dt * gx;
+  cw = w[id] - dt * gz;
+  if (j == g.ny - 1) {
+    cv = T(0);
+  } else {
+    const T gy = T(p[id + (long)g.nz * g.nx] - p0) * g.rdyc[j];
+    cv = v[id] - dt * gy;
+  }
+  u[id] = cu;
+  v[id] = cv;
+  w[id] = cw;
+}
+
 // u1 = us - dt G p (in place on the velocity arrays); the top-wall v plane is 0.
 // One thread per point; the neighbours of p come through the caches.
 template <typename T>
@@ -298,20 +322,59 @@ k_correct(T* u, T* v, T* w, const double* __restrict__ p, Geo<T> g, T dt) {
   const long jk = id / g.nx;
   const int k = int(jk % g.nz);
   const int j = int(jk / g.nz);
-  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
-  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-  const long row = jk * g.nx;
-  const double p0 = p[id];
-  const T gx = T(p[row + ip] - p0) * g.rdx;
-  const T gz = T(p[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz;
-  u[id] = u[id] - dt * gx;
-  w[id] = w[id] - dt * gz;
-  if (j == g.ny - 1) {
-    v[id] = T(0);
-  } else {
-    const T gy = T(p[id + (long)g.nz * g.nx] - p0) * g.rdyc[j];
-    v[id] = v[id] - dt * gy;
+  T cu, cv, cw;
+  correct_point<T>(u, v, w, p, g, dt, id, i, k, j, cu, cv, cw);
+}
+
+// Block reduction of six FP64 per-thread sums in a fixed order (wave shuffles,
+// then the waves in order); thread f < 6 returns sum f.
+template <int TH>
+__device__ __forceinline__ double block_sum6(const double (&sm)[6], double (&red)[6][TH / 64]) {
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    double x = sm[f];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
+    if ((threadIdx.x & 63) == 0) red[f][threadIdx.x >> 6] = x;
   }
+  __syncthreads();
+  double x = 0.0;
+  if (threadIdx.x < 6)
+    for (int k = 0; k < TH / 64; ++k) x += red[threadIdx.x][k];
+  return x;
+}
+
+// The correction of k_correct (same per-point arithmetic) fused with the
+// plane statistics of the corrected fields: block b corrects chunk b % nch of
+// plane b / nch and writes the six FP64 sums of that chunk (u, v, w and their
+// squares; fixed order: strided per-thread sums, then block_sum6) to
+// part[b * 6 + f].  k_stats_gather adds the chunks of each plane in order.
+template <typename T, int TH>
+__global__ void __launch_bounds__(TH)
+k_correct_stats(T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, const double* __restrict__ p, Geo<T> g,
+                T dt, double* __restrict__ part, int nch) {
+  __shared__ double red[6][TH / 64];
+  const int nxz = g.nx * g.nz;
+  const int j = blockIdx.x / nch, c = blockIdx.x % nch;
+  const int len = (nxz + nch - 1) / nch;
+  const int e0 = c * len, e1 = (e0 + len < nxz) ? e0 + len : nxz;
+  const long o = (long)j * nxz;
+  double sm[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int e = e0 + threadIdx.x; e < e1; e += TH) {
+    const int i = e % g.nx, k = e / g.nx;
+    T cu, cv, cw;
+    correct_point<T>(u, v, w, p, g, dt, o + e, i, k, j, cu, cv, cw);
+    const double a = double(cu), b = double(cv), d = double(cw);
+    sm[0] += a;
+    sm[1] += b;
+    sm[2] += d;
+    sm[3] += a * a;
+    sm[4] += b * b;
+    sm[5] += d * d;
+  }
+  const double x = block_sum6<TH>(sm, red);
+  if (threadIdx.x < 6) part[(long)blockIdx.x * 6 + threadIdx.x] = x;
 }
 
 // Plane statistics of a velocity field: for every y-plane j the means over the

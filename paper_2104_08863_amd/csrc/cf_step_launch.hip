@@ -58,6 +58,41 @@ hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T 
   return hipGetLastError();
 }
 
+// st[j*6 + f] (+)= scale * sum over the nch chunks of plane j, in chunk order.
+__global__ void __launch_bounds__(256)
+k_stats_gather(const double* __restrict__ part, double* __restrict__ st, int ny, int nch, double scale,
+               int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ny * 6) return;
+  const int j = t / 6, f = t % 6;
+  double x = 0.0;
+  for (int c = 0; c < nch; ++c) x += part[((long)j * nch + c) * 6 + f];
+  x *= scale;
+  st[t] = accumulate ? st[t] + x : x;
+}
+
+// Chunks per plane of the fused correction + statistics: about 8192 blocks in
+// all, at least 1024 points per chunk.
+int correct_stats_chunks(int nx, int ny, int nz) {
+  const int nxz = nx * nz;
+  int nch = (8192 + ny - 1) / ny;
+  if (nch > nxz / 1024) nch = nxz / 1024;
+  return nch < 1 ? 1 : nch;
+}
+
+template <typename T>
+hipError_t launch_correct_stats(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, double* part, int nch,
+                                double* st, int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL((k_correct_stats<T, 256>), dim3((long)g.ny * nch), dim3(256), 0, s, u, v, w, p, g, dt, part,
+                     nch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = g.ny * 6;
+  hipLaunchKernelGGL(k_stats_gather, dim3((n + 255) / 256), dim3(256), 0, s, part, st, g.ny, nch,
+                     1.0 / double(g.nx * g.nz), accumulate);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, const Geo<T>& g, int accumulate,
                               hipStream_t s) {
@@ -74,7 +109,9 @@ hipError_t launch_plane_stats(const T* u, const T* v, const T* w, double* st, co
                                           hipStream_t);                                                   \
   template hipError_t launch_plane_stats<T>(const T*, const T*, const T*, double*, const Geo<T>&, int, \
                                             hipStream_t);                                            \
-  template hipError_t launch_correct<T>(T*, T*, T*, const double*, const Geo<T>&, T, hipStream_t);
+  template hipError_t launch_correct<T>(T*, T*, T*, const double*, const Geo<T>&, T, hipStream_t);          \
+  template hipError_t launch_correct_stats<T>(T*, T*, T*, const double*, const Geo<T>&, T, double*, int,    \
+                                              double*, int, hipStream_t);
 CF_INST(double)
 CF_INST(float)
 #undef CF_INST
