@@ -286,28 +286,28 @@ k_rk_stage(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict
 #undef CF_RK_STORE
 }
 
-// u1 = us - dt G p at point id = (j, k, i) (in place); the top-wall v plane is
-// 0.  Returns the corrected values.
+// u1 = us - dt G p at point id = (j, k, i), row = (j nz + k) nx (in place; the
+// top-wall v plane is 0), in the statement order of k_correct; returns the
+// corrected values.
 template <typename T>
 __device__ __forceinline__ void correct_point(T* u, T* v, T* w, const double* __restrict__ p, const Geo<T>& g,
-                                              T dt, long id, int i, int k, int j, T& cu, T& cv, T& cw) {
+                                              T dt, long id, long row, int i, int k, int j, T& cu, T& cv, T& cw) {
   const int ip = (i + 1 == g.nx) ? 0 : i + 1;
   const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-  const long row = id - i;
   const double p0 = p[id];
   const T gx = T(p[row + ip] - p0) * g.rdx;
   const T gz = T(p[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz;
   cu = u[id] - dt * gx;
+  u[id] = cu;
   cw = w[id] - dt * gz;
+  w[id] = cw;
   if (j == g.ny - 1) {
     cv = T(0);
   } else {
     const T gy = T(p[id + (long)g.nz * g.nx] - p0) * g.rdyc[j];
     cv = v[id] - dt * gy;
   }
-  u[id] = cu;
   v[id] = cv;
-  w[id] = cw;
 }
 
 // u1 = us - dt G p (in place on the velocity arrays); the top-wall v plane is 0.
@@ -322,8 +322,20 @@ k_correct(T* u, T* v, T* w, const double* __restrict__ p, Geo<T> g, T dt) {
   const long jk = id / g.nx;
   const int k = int(jk % g.nz);
   const int j = int(jk / g.nz);
-  T cu, cv, cw;
-  correct_point<T>(u, v, w, p, g, dt, id, i, k, j, cu, cv, cw);
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const long row = jk * g.nx;
+  const double p0 = p[id];
+  const T gx = T(p[row + ip] - p0) * g.rdx;
+  const T gz = T(p[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz;
+  u[id] = u[id] - dt * gx;
+  w[id] = w[id] - dt * gz;
+  if (j == g.ny - 1) {
+    v[id] = T(0);
+  } else {
+    const T gy = T(p[id + (long)g.nz * g.nx] - p0) * g.rdyc[j];
+    v[id] = v[id] - dt * gy;
+  }
 }
 
 // Block reduction of six FP64 per-thread sums in a fixed order (wave shuffles,
@@ -364,7 +376,7 @@ k_correct_stats(T* __restrict__ u, T* __restrict__ v, T* __restrict__ w, const d
   for (int e = e0 + threadIdx.x; e < e1; e += TH) {
     const int i = e % g.nx, k = e / g.nx;
     T cu, cv, cw;
-    correct_point<T>(u, v, w, p, g, dt, o + e, i, k, j, cu, cv, cw);
+    correct_point<T>(u, v, w, p, g, dt, o + e, o + e - i, i, k, j, cu, cv, cw);
     const double a = double(cu), b = double(cv), d = double(cw);
     sm[0] += a;
     sm[1] += b;
