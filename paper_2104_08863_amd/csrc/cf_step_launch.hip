@@ -71,11 +71,11 @@ k_stats_gather(const double* __restrict__ part, double* __restrict__ st, int ny,
   st[t] = accumulate ? st[t] + x : x;
 }
 
-// Chunks per plane of the fused correction + statistics: about 8192 blocks in
+// Chunks per plane of the fused correction + statistics: about 32768 blocks in
 // all, at least 1024 points per chunk.
 int correct_stats_chunks(int nx, int ny, int nz) {
   const int nxz = nx * nz;
-  int nch = (8192 + ny - 1) / ny;
+  int nch = (32768 + ny - 1) / ny;
   if (nch > nxz / 1024) nch = nxz / 1024;
   return nch < 1 ? 1 : nch;
 }
