@@ -58,7 +58,7 @@ typedef struct {
   int precision;      /* CF_FP64 (all arithmetic FP64) or CF_MIXED (FP32 transforms and
                          bulk wall-normal solves, FP64 low-wavenumber lines and residual) */
   int n_parts;        /* PDD partitions per wall-normal line; 0 = automatic. ny/n_parts
-                         must be one of 1,2,3,4,6,8,12,16 */
+                         must be one of 1,2,3,4,6,8,12,16 (CF_MIXED: also 24, 32) */
   double drop_tol;    /* lines whose PDD corner terms are all <= drop_tol use the dropped
                          (2x2) reduced system; the others the exact one.  < 0 = default
                          (1e-15 FP64, 1e-7 mixed) */
@@ -79,7 +79,7 @@ typedef struct {
 /* CF_PLAN_TUNE_PARTS: choose the partitioning by measurement (Section 2.2 leaves
    the count P and the placement to the solver): at creation the plan times the
    partitioned solve for every admissible P (ny = P*M, M in {1,2,3,4,6,8,12,16},
-   P <= 64) and every block of lines_per_block = 4, 8, ..., 256 lines with
+   in CF_MIXED also 24 and 32, P <= 64) and every block of lines_per_block = 4, 8, ..., 256 lines with
    64 <= lines_per_block * P <= 512 that fits in LDS (five launches each, after
    two warm-up launches, in place on zeros in the plan's workspace), keeps the
    fastest and sets the drop threshold for its P (each candidate's accuracy
@@ -110,7 +110,8 @@ void cf_options_default(cf_options* opt);
  * Create a plan on the current HIP device (Section 2 problem setup: Eq. (8)-(9)
  * operator, modified wavenumbers, PDD partitioning of Section 2.2).
  * nx, nz: even, 2^a or 3*2^a, nx/2 and nz in [2, 2048] (nz >= 2).
- * ny >= 2 and ny = P*M with M in {1,2,3,4,6,8,12,16} and P <= 64.
+ * ny >= 2 and ny = P*M with M in {1,2,3,4,6,8,12,16} (CF_MIXED: also 24, 32) and
+ * P <= 64; the automatic P is the fewest such partitions, preferring powers of two.
  * y_faces: host, ny+1 strictly increasing finite values (walls at both ends).
  * opt: NULL for defaults.  On success *out receives the plan; on failure *out is
  * set to NULL and nothing is leaked.

@@ -97,7 +97,7 @@ hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, 
                                 const double* cp, const double* dy, const int* lines, int n_lines,
                                 int ny, int nz, hipStream_t s);
 
-bool ysolve_m_compiled(int m);
+bool ysolve_m_compiled(int m, bool fp64);
 
 template <typename T>
 struct Geo;

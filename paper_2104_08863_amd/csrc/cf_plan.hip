@@ -249,7 +249,8 @@ double corner_delta(const cf_plan* pl, double k2) {
   case MM:          \
     cf::pdd_local<MM, double>(ar, cr, k2, d.data(), v.data(), w.data()); \
     break;
-      CF_CASE(1) CF_CASE(2) CF_CASE(3) CF_CASE(4) CF_CASE(6) CF_CASE(8) CF_CASE(12) CF_CASE(16)
+      CF_CASE(1) CF_CASE(2) CF_CASE(3) CF_CASE(4) CF_CASE(6) CF_CASE(8) CF_CASE(12) CF_CASE(16) CF_CASE(24)
+      CF_CASE(32)
 #undef CF_CASE
       default:
         return INFINITY;
@@ -291,16 +292,19 @@ void set_partitions(cf_plan* pl, int P, int LB) {
       if (pl->kx2[kx] + pl->kz2[kz] >= pl->k2drop) ++pl->n_drop;
 }
 
-int auto_parts(int ny) {
-  // fewest partitions with at most 16 rows each, preferring powers of two
+int auto_parts(int ny, bool fp64) {
+  // fewest partitions with a compiled row count (at most 16 rows in FP64, 32 in
+  // FP32), preferring powers of two
   for (int P = 1; P <= 64; P *= 2)
-    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P)) return P;
+    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64)) return P;
   for (int P = 1; P <= 64; ++P)
-    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P)) return P;
+    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64)) return P;
   return 0;
 }
 
-bool parts_ok(int ny, int P) { return P >= 1 && P <= 64 && ny % P == 0 && cf::ysolve_m_compiled(ny / P); }
+bool parts_ok(int ny, int P, bool fp64) {
+  return P >= 1 && P <= 64 && ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64);
+}
 
 cf_status check_plan(const cf_plan* pl) {
   if (!pl) return fail(CF_ERR_ARG, "plan is NULL");
@@ -716,7 +720,7 @@ cf_status tune_partitions(cf_plan* pl, size_t lds_max) {
   pl->tune.clear();
   size_t best = 0;
   for (int P = 1; P <= 64; ++P) {
-    if (!parts_ok(pl->ny, P)) continue;
+    if (!parts_ok(pl->ny, P, fp64)) continue;
     for (int LB = 4; LB <= 256; LB *= 2) {
       if (LB * P < 64 || LB * P > 512 || cf::ysolve_lds_needed(pl->ny, P, LB, fp64) > lds_max) continue;
       set_partitions(pl, P, LB);
@@ -795,9 +799,11 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   if (tune && (opt.n_parts != 0 || opt.lines_per_block != 0 || (opt.flags & CF_PLAN_Y_DCT)))
     return fail(CF_ERR_ARG, "CF_PLAN_TUNE_PARTS needs n_parts = 0, lines_per_block = 0 and the partitioned solve");
   int P = opt.n_parts;
-  if (P == 0) P = auto_parts(ny);
-  if (P == 0 || !parts_ok(ny, P))
-    return fail(CF_ERR_UNSUPPORTED, "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16}");
+  const bool fp64 = opt.precision == CF_FP64;
+  if (P == 0) P = auto_parts(ny, fp64);
+  if (P == 0 || !parts_ok(ny, P, fp64))
+    return fail(CF_ERR_UNSUPPORTED, fp64 ? "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16}"
+                                         : "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16,24,32}");
   if (opt.lines_per_block < 0 || opt.lines_per_block * P > 512)
     return fail(CF_ERR_ARG, "lines_per_block must be >= 0 with lines_per_block * n_parts <= 512");
   const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P);

@@ -4,14 +4,19 @@
 
 namespace cf {
 
+// Rows per partition compiled for both precisions, and the longer partitions
+// compiled for FP32 only (in FP64 their rows no longer fit the registers).
 #define CF_FOR_EACH_M(X) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16)
+#define CF_FOR_EACH_M_FP32(X) X(24) X(32)
 
-bool ysolve_m_compiled(int m) {
+bool ysolve_m_compiled(int m, bool fp64) {
   switch (m) {
 #define CF_CASE(M) case M:
     CF_FOR_EACH_M(CF_CASE)
-#undef CF_CASE
     return true;
+    CF_FOR_EACH_M_FP32(CF_CASE)
+    return !fp64;
+#undef CF_CASE
     default:
       return false;
   }
@@ -71,8 +76,26 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
     CF_FOR_EACH_M(CF_CASE)
 #undef CF_CASE
     default:
-      return hipErrorInvalidValue;
+      break;
   }
+  if constexpr (std::is_same<T, float>::value) {
+    switch (y.M) {
+#define CF_CASE(M)                  \
+  case M:                           \
+    if (y.mode == kSlabLocal)       \
+      CF_LAUNCH(M, kSlabLocal);     \
+    else if (y.mode == kSlabFinish) \
+      CF_LAUNCH(M, kSlabFinish);    \
+    else                            \
+      CF_LAUNCH(M, kWhole);         \
+    return hipGetLastError();
+      CF_FOR_EACH_M_FP32(CF_CASE)
+#undef CF_CASE
+      default:
+        break;
+    }
+  }
+  return hipErrorInvalidValue;
 #undef CF_LAUNCH
 }
 

@@ -12,6 +12,7 @@ from paper_2104_08863_amd import synth
 pytestmark = pytest.mark.gpu
 
 M_SET = (1, 2, 3, 4, 6, 8, 12, 16)
+M_SET_FP32 = M_SET + (24, 32)   # mixed precision also compiles longer partitions
 
 
 def dev():
@@ -22,8 +23,9 @@ def rel(a, b):
     return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
 
 
-def admissible(ny):
-    return {(P, lb) for P in range(1, 65) if ny % P == 0 and ny // P in M_SET
+def admissible(ny, mixed=False):
+    ms = M_SET_FP32 if mixed else M_SET
+    return {(P, lb) for P in range(1, 65) if ny % P == 0 and ny // P in ms
             for lb in (4, 8, 16, 32, 64, 128, 256) if 64 <= lb * P <= 512}
 
 
@@ -71,7 +73,9 @@ def test_tuned_partitioning_mixed():
     nx, ny, nz = 128, 192, 96
     pl, box = make(nx, ny, nz, 2.0, precision="mixed", tune_parts=True)
     rows = pl.partition_timings()
-    assert {(P, lb) for P, lb, _ in rows} <= admissible(ny)
+    got = {(P, lb) for P, lb, _ in rows}
+    assert got <= admissible(ny, mixed=True)
+    assert any(ny // P > 16 for P, _ in got)      # the FP32-only 24- and 32-row partitions are candidates
     info = pl.info()
     assert (info["n_parts"], info["lines_per_block"]) == min(rows, key=lambda r: r[2])[:2]
     f = synth.uniform_rhs(nx, ny, nz, seed=5)
