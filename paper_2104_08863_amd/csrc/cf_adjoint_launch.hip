@@ -4,14 +4,27 @@
 
 namespace cf {
 
-// Tile: 32 x 8 columns, chunks of 32 planes (six LDS fields x three planes;
-// 32-plane chunks measured 2 % faster than 64 and 16 on 1024x256x512 FP64).
-constexpr int ADJ_TX = 32, ADJ_TZ = 8, ADJ_CY = 32;
+// Tile of the transposed stencil (six LDS fields x three planes) and chunks of
+// 32 planes.  FP64: 32 x 8 columns (51 KB of LDS, three blocks per CU; 64 x 8
+// and 32 x 16 were slower, 32-plane chunks 2 % faster than 64 and 16).  FP32:
+// 64 x 8 columns, 36 % faster than 32 x 8 and ahead of 64 x 16, 128 x 4,
+// 128 x 8 and 32 x 16 on 512x384x512 (half the LDS per value lets the wider
+// tile keep its occupancy while cutting the halo share).
+template <typename T>
+struct AdjTile {
+  static constexpr int TX = 32, TZ = 8;
+};
+template <>
+struct AdjTile<float> {
+  static constexpr int TX = 64, TZ = 8;
+};
+constexpr int ADJ_CY = 32;
 
 template <typename T>
 hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, const T* av, const T* aw,
                               const T* bu, const T* bv, const T* bw, T c1, T c2, const AdjGeo<T>& g, T nu, T s,
                               int add, T* gu, T* gv, T* gw, hipStream_t st) {
+  constexpr int ADJ_TX = AdjTile<T>::TX, ADJ_TZ = AdjTile<T>::TZ;
   AdjPtrs P{u, v, w, au, av, aw, bu, bv, bw, gu, gv, gw};
   const long blocks = (long)((g.g.nx + ADJ_TX - 1) / ADJ_TX) * ((g.g.nz + ADJ_TZ - 1) / ADJ_TZ) *
                       ((g.g.ny + ADJ_CY - 1) / ADJ_CY);
