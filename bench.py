@@ -550,7 +550,7 @@ def main():
         print(json.dumps({"copy_bytes": n * 8, "copies": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
               "the multi-GPU split is a design note, not built", file=sys.stderr)
         sys.exit(2)
 
