@@ -551,7 +551,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
-              "the multi-GPU split is a design note, not built", file=sys.stderr)
+              "the exchange between devices is not part of it", file=sys.stderr)
         sys.exit(2)
 
     import torch
