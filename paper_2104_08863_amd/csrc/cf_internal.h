@@ -82,7 +82,7 @@ struct YLaunch {
 };
 
 // Default lines per block of the partitioned solve for P partitions.
-int ysolve_default_lb(int P);
+int ysolve_default_lb(int P, int M);
 // Dynamic LDS of one partitioned-solve block.
 size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64);
 

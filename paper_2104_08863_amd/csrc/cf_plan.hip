@@ -806,7 +806,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
                                          : "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16,24,32}");
   if (opt.lines_per_block < 0 || opt.lines_per_block * P > 512)
     return fail(CF_ERR_ARG, "lines_per_block must be >= 0 with lines_per_block * n_parts <= 512");
-  const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P);
+  const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P, ny / P);
   if (opt.precision == CF_MIXED) {
     if (opt.fp64_kx < 1 || opt.fp64_kz < 1) return fail(CF_ERR_ARG, "fp64_kx and fp64_kz must be >= 1");
     if (opt.refine_passes < 0 || opt.refine_passes > 8) return fail(CF_ERR_ARG, "refine_passes must be in [0, 8]");

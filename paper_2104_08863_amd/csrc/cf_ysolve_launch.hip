@@ -22,13 +22,15 @@ bool ysolve_m_compiled(int m, bool fp64) {
   }
 }
 
-// Default lines per block: about 256 threads per block with 8 to 16 lines,
-// and at least one wave.  Measured on MI355X for the default partition counts
-// (P = 8, 16, 32 at ny = 128, 256, 512; P = 64 at ny = 768) this is the fastest
-// block or within 10 % of it; other shapes can be chosen by measurement.
-int ysolve_default_lb(int P) {
+// Default lines per block: about 256 threads per block with 8 to 16 lines (to
+// 32 for the FP32-only partitions of more than 16 rows), and at least one
+// wave.  Measured on MI355X for the default partitionings of the workload grids
+// this is the fastest block or within 2 % of it; other shapes can be chosen by
+// measurement.
+int ysolve_default_lb(int P, int M) {
+  const int hi = M > 16 ? 32 : 16;
   int lb = 256 / P;
-  lb = lb < 8 ? 8 : (lb > 16 ? 16 : lb);
+  lb = lb < 8 ? 8 : (lb > hi ? hi : lb);
   if (lb * P < 64) lb = (64 + P - 1) / P;
   return lb;
 }
@@ -41,7 +43,7 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   ya.nz = y.nz;
   ya.nkx = y.nkx;
   ya.P = y.P;
-  ya.LB = y.LB > 0 ? y.LB : ysolve_default_lb(y.P);
+  ya.LB = y.LB > 0 ? y.LB : ysolve_default_lb(y.P, y.M);
   ya.nlines = y.nlines;
   ya.skip_kx = y.skip_kx;
   ya.skip_kz = y.skip_kz;
