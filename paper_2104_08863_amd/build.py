@@ -32,6 +32,10 @@ HIP_FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 HOST_SOURCES = ["cf_host_emul.cpp"]
+# Per-source extra flags.  The step kernels (fused RK2 pass, split stages,
+# correction) take the instruction-level-parallelism scheduling strategy: the
+# fused pass is latency-bound and runs 2 % faster with it (same results).
+EXTRA_FLAGS = {"cf_step_launch.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def _hip_sources():
@@ -52,7 +56,7 @@ def build(verbose: bool = True, jobs: int | None = None) -> None:
 
     def comp(src_obj):
         src, obj = src_obj
-        return src, _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        return src, _run([HIPCC, *HIP_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
 
     with cf.ThreadPoolExecutor(jobs) as ex:
         results = list(ex.map(comp, zip(srcs, objs)))
