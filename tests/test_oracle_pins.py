@@ -427,3 +427,246 @@ def test_uniform_y_solve_is_a_periodic_solve_of_the_even_extension():
     p = np.fft.ifft(ph, axis=0)[:ny]
     p = np.fft.ifft(np.fft.ifft(p, axis=1), axis=2).real
     assert np.abs(p - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- staggered D and G positions
+def _staggered_positions(box):
+    """Coordinates of the staggered unknowns (the layout of Fig. 2 as the C
+    interface states it): centres x_i = i dx, z_k = k dz, yc_j the face
+    midpoints; u at x_{i+1/2}, v at the face y_faces[j+1], w at z_{k+1/2}."""
+    xc = np.arange(box.nx) * box.dx
+    zc = np.arange(box.nz) * box.dz
+    yf = box.y_faces
+    yc = 0.5 * (yf[1:] + yf[:-1])
+    return xc, xc + 0.5 * box.dx, zc, zc + 0.5 * box.dz, yc, yf
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (3, 2), (5, 7)])
+def test_divergence_and_gradient_sit_at_the_staggered_positions(m, n):
+    """Closed forms of the centred differences on the staggered grid: for
+    u = sin(kx x) sampled on the u faces, D gives 2 sin(kx dx/2)/dx cos(kx x_i)
+    at the cell centre x_i; for p = sin(kx x) at the centres, G gives
+    2 sin(kx dx/2)/dx cos(kx x_{i+1/2}) on the u face (z alike).  In y, D is the
+    difference of v between the two faces of the cell over its height and G the
+    difference of p between the two centres over their distance.  A stencil
+    shifted by one cell moves the cosine's argument by dx and fails."""
+    nx, ny, nz = 24, 10, 18
+    box = make_box(nx, ny, nz, gamma=2.0, lx=2 * np.pi, lz=2 * np.pi)
+    xc, xf, zc, zf, yc, yf = _staggered_positions(box)
+    kx, kz = float(m), float(n)
+    sx = 2 * np.sin(kx * box.dx / 2) / box.dx
+    sz = 2 * np.sin(kz * box.dz / 2) / box.dz
+    V = lambda y: (1 - y ** 2) * (1 + 0.3 * y)  # noqa: E731  vanishes on both walls
+    ones = np.ones((ny, nz, nx))
+    u = np.sin(kx * xf)[None, None, :] * ones
+    v = V(yf[1:])[:, None, None] * ones
+    w = np.sin(kz * zf)[None, :, None] * ones
+    d = O.divergence(T(u), T(v), T(w), box).numpy()
+    want = (sx * np.cos(kx * xc)[None, None, :] + ((V(yf[1:]) - V(yf[:-1])) / np.diff(yf))[:, None, None]
+            + sz * np.cos(kz * zc)[None, :, None])
+    assert np.abs(d - want).max() < 1e-12 * np.abs(want).max()
+    P = lambda y: np.cos(2.0 * y) + y  # noqa: E731
+    p = (np.sin(kx * xc)[None, None, :] + np.sin(kz * zc)[None, :, None] + P(yc)[:, None, None]) * ones
+    gu, gv, gw = (g.numpy() for g in O.gradient(T(p), box))
+    assert np.abs(gu - sx * np.cos(kx * xf)[None, None, :]).max() < 1e-12 * sx
+    assert np.abs(gw - sz * np.cos(kz * zf)[None, :, None]).max() < 1e-12 * sz
+    want_v = (P(yc[1:]) - P(yc[:-1])) / (yc[1:] - yc[:-1])
+    assert np.abs(gv[:-1] - want_v[:, None, None]).max() < 1e-12 * np.abs(want_v).max()
+    assert (gv[-1] == 0).all()
+
+
+def test_divergence_and_gradient_converge_at_second_order():
+    """D and G of smooth fields tend to the analytic divergence and gradient at
+    the staggered positions with second-order error on a stretched grid."""
+    errs_d, errs_g = [], []
+    for n in (16, 32, 64):
+        box = make_box(n, n, n, gamma=1.5, lx=2 * np.pi, lz=2 * np.pi)
+        xc, xf, zc, zf, yc, yf = _staggered_positions(box)
+        # fields as functions on explicit position grids (ny, nz, nx)
+        g = lambda ys, zs, xs: (ys[:, None, None], zs[None, :, None], xs[None, None, :])  # noqa: E731
+        y_, z_, x_ = g(yc, zc, xf)
+        u = np.sin(x_) * np.cos(z_) * (1 - y_ ** 2)
+        y_, z_, x_ = g(yf[1:], zc, xc)
+        v = np.cos(x_) * np.sin(z_) * (1 - y_ ** 2) * (1 + 0.5 * y_)
+        y_, z_, x_ = g(yc, zf, xc)
+        w = np.sin(x_ + z_) * np.cos(y_)
+        d = O.divergence(T(u), T(v), T(w), box).numpy()
+        y_, z_, x_ = g(yc, zc, xc)
+        dv = np.cos(x_) * np.sin(z_) * (-2 * y_ * (1 + 0.5 * y_) + 0.5 * (1 - y_ ** 2))
+        want = np.cos(x_) * np.cos(z_) * (1 - y_ ** 2) + dv + np.cos(x_ + z_) * np.cos(y_)
+        errs_d.append(np.abs(d - want).max())
+        p = np.sin(2 * x_) * np.cos(z_) + np.sin(y_) * np.cos(x_ - z_)
+        gu, gv, gw = (q.numpy() for q in O.gradient(T(p), box))
+        y_, z_, x_ = g(yc, zc, xf)
+        e = np.abs(gu - (2 * np.cos(2 * x_) * np.cos(z_) - np.sin(y_) * np.sin(x_ - z_))).max()
+        y_, z_, x_ = g(yf[1:-1], zc, xc)
+        e = max(e, np.abs(gv[:-1] - np.cos(y_) * np.cos(x_ - z_)).max())
+        y_, z_, x_ = g(yc, zf, xc)
+        e = max(e, np.abs(gw - (-np.sin(2 * x_) * np.sin(z_) + np.sin(y_) * np.sin(x_ - z_))).max())
+        errs_g.append(e)
+    for errs in (errs_d, errs_g):
+        assert errs[1] < 0.3 * errs[0] and errs[2] < 0.3 * errs[1], errs
+
+
+# ---------------------------------------------------------------- momentum RHS against analytic fields
+class _Sep:
+    """A separable field f(x) g(y) h(z) with its derivatives (f, f', f''), ..."""
+
+    def __init__(self, fx, gy, hz):
+        self.f, self.g, self.h = fx, gy, hz
+
+    def val(self, x, y, z, dx=0, dy=0, dz=0):
+        return self.f[dx](x) * self.g[dy](y) * self.h[dz](z)
+
+
+def _trig(k, phase=0.0):
+    return (lambda s: np.sin(k * s + phase), lambda s: k * np.cos(k * s + phase),
+            lambda s: -k * k * np.sin(k * s + phase))
+
+
+def _poly(c):
+    """Polynomial with coefficients c (lowest first) and its two derivatives."""
+    p = np.polynomial.Polynomial(c)
+    return (p, p.deriv(1), p.deriv(2))
+
+
+# u, w vanish on both walls (no slip), v vanishes on both walls.
+_U = _Sep(_trig(1.0), _poly([1, 0, -1]), _trig(1.0, 0.5 * np.pi))           # cos z
+_V = _Sep(_trig(1.0, 0.5 * np.pi), _poly([1, 0.5, -1, -0.5]), _trig(2.0))     # (1-y^2)(1+y/2)
+_W = _Sep(_trig(2.0, 0.3), _poly([0, 1, 0, -1]), _trig(1.0, 1.0))             # y(1-y^2)
+
+
+def _prod_deriv(a, b, x, y, z, axis):
+    """d/d(axis) of the product a*b at the points."""
+    d = [0, 0, 0]
+    d[axis] = 1
+    return a.val(x, y, z, *d) * b.val(x, y, z) + a.val(x, y, z) * b.val(x, y, z, *d)
+
+
+def _lap(a, x, y, z):
+    return a.val(x, y, z, 2, 0, 0) + a.val(x, y, z, 0, 2, 0) + a.val(x, y, z, 0, 0, 2)
+
+
+def _analytic_rhs(x, y, z, comp, nu, fx):
+    """-div(u u_comp) + nu lap(u_comp) + fx [comp == x] at the points."""
+    F = (_U, _V, _W)
+    q = F[comp]
+    n = sum(_prod_deriv(F[ax], q, x, y, z, ax) for ax in range(3))
+    return -n + nu * _lap(q, x, y, z) + (fx if comp == 0 else 0.0)
+
+
+def _sample(box):
+    xc, xf, zc, zf, yc, yf = _staggered_positions(box)
+    g = lambda ys, zs, xs: (xs[None, None, :], ys[:, None, None], zs[None, :, None])  # noqa: E731
+    pos = (g(yc, zc, xf), g(yf[1:], zc, xc), g(yc, zf, xc))
+    ones = np.ones((box.ny, box.nz, box.nx))
+    fields = [F.val(*p) * ones for F, p in zip((_U, _V, _W), pos)]
+    fields[1][-1] = 0.0
+    return fields, pos
+
+
+def test_momentum_rhs_converges_to_the_analytic_rhs():
+    """Every component of R(u) = -div(u u) + nu lap u + fx e_x converges at
+    second order to the analytic value on a stretched grid, at every interior
+    unknown (the u and w wall cells carry the mirrored-ghost O(1) error of the
+    viscous term and are left out; their advective part is checked separately
+    below).  Pins each flux term of the three momentum components, the
+    interpolations and the wall-normal viscous terms (v included)."""
+    nu, fx = 0.7, 0.3
+    errs = {c: [] for c in range(3)}
+    for n in (16, 32, 64):
+        box = make_box(n, n, n, gamma=1.5, lx=2 * np.pi, lz=2 * np.pi)
+        fields, pos = _sample(box)
+        r = O.momentum_rhs(*(T(q) for q in fields), box, nu, fx)
+        for c in range(3):
+            want = _analytic_rhs(*pos[c], c, nu, fx) * np.ones_like(fields[c])
+            got = r[c].numpy()
+            sl = slice(0, n - 1) if c == 1 else slice(1, n - 1)
+            errs[c].append(np.abs(got[sl] - want[sl]).max())
+    for c in range(3):
+        e = errs[c]
+        assert e[1] < 0.32 * e[0] and e[2] < 0.32 * e[1], (c, e)
+        assert e[2] < 2e-2, (c, e)
+
+
+def test_advection_converges_including_the_wall_cells():
+    """The advective part alone (nu = 0) converges at second order in every
+    cell, wall cells included (no ghost enters the flux form: the wall-normal
+    fluxes through the walls vanish with v)."""
+    errs = {c: [] for c in range(3)}
+    for n in (16, 32, 64):
+        box = make_box(n, n, n, gamma=1.5, lx=2 * np.pi, lz=2 * np.pi)
+        fields, pos = _sample(box)
+        N = O.advection(*(T(q) for q in fields), box)
+        for c in range(3):
+            want = -_analytic_rhs(*pos[c], c, 0.0, 0.0) * np.ones_like(fields[c])
+            got = N[c].numpy()
+            sl = slice(0, n - 1) if c == 1 else slice(0, n)
+            errs[c].append(np.abs(got[sl] - want[sl]).max())
+    for c in range(3):
+        e = errs[c]
+        assert e[1] < 0.32 * e[0] and e[2] < 0.32 * e[1], (c, e)
+
+
+def test_wall_normal_interpolation_is_exact_for_linear_profiles():
+    """Linear interpolation to a face weighted by the distances to the two
+    neighbouring centres reproduces a field linear in y exactly on any grid;
+    through the x-momentum flux it makes the wall-normal flux difference of
+    u v equal the exact cell difference of the product for u linear in y."""
+    import oracle.chanflow_oracle as OC
+    box = make_box(6, 20, 4, gamma=2.5)
+    xc, xf, zc, zf, yc, yf = _staggered_positions(box)
+    q = np.broadcast_to((0.7 - 2.3 * yc)[:, None, None], (20, 4, 6)).copy()
+    got = OC._interp_y_to_face(T(q), box).numpy()[:, 0, 0]
+    want = 0.7 - 2.3 * yf[1:-1]
+    assert np.abs(got - want).max() < 1e-14
+    # u = 0.7 - 2.3 y (uniform in x, z), v = 1 - y^2 on the faces, w = 0
+    ones = np.ones((20, 4, 6))
+    u = (0.7 - 2.3 * yc)[:, None, None] * ones
+    v = (1 - yf[1:] ** 2)[:, None, None] * ones
+    v[-1] = 0
+    nxu = O.advection(T(u), T(v), T(0 * u), box)[0].numpy()[:, 0, 0]
+    g = (0.7 - 2.3 * yf) * (1 - yf ** 2)       # u v on every face (0 on the walls)
+    assert np.abs(nxu - np.diff(g) / np.diff(yf)).max() < 1e-12
+
+
+def test_heun_predictor_has_third_order_local_error():
+    """The RK2 predictor is Heun's method for du/dt = R(u): its one-step error
+    against a tight classical RK4 integration falls by 8 when dt halves, in
+    every component (a component advanced with the first stage's slope alone
+    falls by 4)."""
+    import oracle.chanflow_oracle as OC
+    nx, ny, nz = 8, 8, 8
+    yf = synth.tanh_faces(ny, 1.5)
+    box = O.Box(nx, ny, nz, 2 * np.pi, np.pi, yf)
+    u, v, w = (T(q) for q in synth.perturbed_poiseuille(nx, ny, nz, yf, seed=3, amp=0.3))
+    nu, fx = 0.02, 0.06
+
+    def wall(vv):
+        vv = vv.clone()
+        vv[-1] = 0
+        return vv
+
+    def rk4(s, dt, n):
+        h = dt / n
+        s = [s[0], wall(s[1]), s[2]]
+        for _ in range(n):
+            def f(a):
+                return O.momentum_rhs(a[0], wall(a[1]), a[2], box, nu, fx)
+            k1 = f(s)
+            k2 = f([q + 0.5 * h * k for q, k in zip(s, k1)])
+            k3 = f([q + 0.5 * h * k for q, k in zip(s, k2)])
+            k4 = f([q + h * k for q, k in zip(s, k3)])
+            s = [q + h / 6 * (a + 2 * b + 2 * c + d) for q, a, b, c, d in zip(s, k1, k2, k3, k4)]
+            s[1] = wall(s[1])
+        return s
+
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        h = OC.rk2_predictor(u, v, w, box, dt, nu, fx)
+        r = rk4((u, v, w), dt, 16)
+        errs.append([float((a - b).abs().max()) for a, b in zip(h, r)])
+    for c in range(3):
+        for k in range(2):
+            ratio = errs[k][c] / errs[k + 1][c]
+            assert 7.0 < ratio < 9.0, (c, errs)
