@@ -1331,9 +1331,15 @@ cf_status cf_projection_step_adjoint(cf_plan* pl, const void* u, const void* v, 
   const void* ptrs[9] = {u, v, w, gu1, gv1, gw1, gu, gv, gw};
   const char* names[9] = {"u", "v", "w", "gu1", "gv1", "gw1", "gu", "gv", "gw"};
   for (int q = 0; q < 9; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  // the last transposed-stencil pass writes g while it reads the step input's
+  // neighbourhoods, so no byte of an output may lie in an input array
+  const uintptr_t fbytes = (uintptr_t)pl->nx * pl->ny * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
   for (int q = 6; q < 9; ++q)
-    for (int r = 0; r < 3; ++r)
-      if (ptrs[q] == ptrs[r]) return fail(CF_ERR_ARG, "the gradient output must not alias the step input");
+    for (int r = 0; r < 3; ++r) {
+      const uintptr_t x = reinterpret_cast<uintptr_t>(ptrs[q]), y = reinterpret_cast<uintptr_t>(ptrs[r]);
+      if (x < y + fbytes && y < x + fbytes)
+        return fail(CF_ERR_ARG, "the gradient output must not overlap the step input");
+    }
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
   if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -194,3 +194,22 @@ def test_mixed_adjoint_scaled_copy_of_2048x768x2048():
     for a, b, name in zip(fm, f64, "uvw"):
         e = float(torch.linalg.vector_norm(a.double() - b) / torch.linalg.vector_norm(b))
         assert e <= 2e-6, f"step {name}: {e:.3e}"
+
+
+def test_step_adjoint_rejects_outputs_overlapping_the_input():
+    """A gradient output that shares any byte with a step-input array (not only
+    the same start address) is an argument error, returned before any work."""
+    from paper_2104_08863_amd import _lib as L
+    pl, box = setup(16, 8, 8, 2.0)
+    n = 8 * 8 * 16
+    big = torch.zeros(4 * n + 16, dtype=torch.float64, device=dev())
+    u, v, w = (big[k * n:(k + 1) * n].view(8, 8, 16) for k in range(3))
+    g1 = tuple(torch.ones(8, 8, 16, dtype=torch.float64, device=dev()) for _ in range(3))
+    ok = tuple(torch.empty(8, 8, 16, dtype=torch.float64, device=dev()) for _ in range(3))
+    # gv starts 16 values into v (a partial overlap), gu and gw are separate
+    gv = big[n + 16:2 * n + 16].view(8, 8, 16)
+    with pytest.raises(L.ChanflowError) as e:
+        pl.projection_step_adjoint(u, v, w, *g1, 1e-3, 0.01, 0.03, out=(ok[0], gv, ok[2]))
+    assert e.value.status == L.CF_ERR_ARG
+    torch.cuda.synchronize()
+    assert bool((big == 0).all())
