@@ -273,6 +273,23 @@ cf_status cf_solve_spectral_slabs(cf_plan* plan, int n_slabs, const void* fhat, 
                                   void* stream);
 
 /*
+ * cf_solve_spectral_slabs without the iface argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the interface rows go to a fixed device
+ * array of the library (32 MiB; each device the library runs on holds its own
+ * copy until the process ends, its address taken at plan creation).  The call
+ * makes no device allocation and records no per-kernel timing.  Plans whose
+ * interface rows (cf_plan_info.slab_iface_bytes) exceed 32 MiB are rejected
+ * with CF_ERR_ARG before any work is enqueued.  Every call on a device shares
+ * that device's array: calls that overlap on one device (several streams, or
+ * several host threads) race and must be serialised by the caller.  The array
+ * keeps the last call's contents; every value a call reads from it is written
+ * earlier in the same call, so nothing needs clearing.  Other arguments and the
+ * result are as for cf_solve_spectral_slabs.
+ */
+cf_status cf_solve_spectral_slabs_noalloc(cf_plan* plan, int n_slabs, const void* fhat, void* phat, void* stream);
+
+/*
  * Per-kernel timing with HIP events (measurement support).  While enabled, every
  * kernel launch of the plan is bracketed by two events recorded on the launch
  * stream; cf_plan_get_timing synchronises on them and returns the accumulated

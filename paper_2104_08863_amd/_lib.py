@@ -59,6 +59,7 @@ SIGNATURES = {
     "cf_inverse_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral_slabs": (_I, [_P, _I, _P, _P, _P, _P]),
+    "cf_solve_spectral_slabs_noalloc": (_I, [_P, _I, _P, _P, _P]),
     "cf_plan_set_timing": (_I, [_P, _I]),
     "cf_plan_reset_timing": (_I, [_P]),
     "cf_plan_get_timing": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_longlong)]),

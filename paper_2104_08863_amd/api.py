@@ -289,3 +289,12 @@ class Plan:
         L.check(L.lib().cf_solve_spectral_slabs(self._h, int(n_slabs), _ptr(fhat), _ptr(out), _ptr(iface),
                                                 _stream()), "cf_solve_spectral_slabs")
         return out
+
+    def solve_spectral_slabs_noalloc(self, fhat: torch.Tensor, n_slabs: int, out: torch.Tensor) -> torch.Tensor:
+        """solve_spectral_slabs with the interface rows in the library's static
+        device array (no device allocation in the call; out must be given)."""
+        self._spec(fhat, "fhat")
+        self._spec(out, "out")
+        L.check(L.lib().cf_solve_spectral_slabs_noalloc(self._h, int(n_slabs), _ptr(fhat), _ptr(out), _stream()),
+                "cf_solve_spectral_slabs_noalloc")
+        return out

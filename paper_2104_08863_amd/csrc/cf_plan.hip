@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,14 @@
 #include "cf_step_kernels.h"
 
 using cf::cx;
+
+// Interface rows of cf_solve_spectral_slabs_noalloc: a fixed device array (each
+// device the library runs on holds its own copy until the process ends), so
+// that entry point allocates nothing.  Host code must not pass this name to a
+// kernel or a copy: it is a host-side stand-in; the device address of each
+// device's copy is taken once per device at plan creation (scratch_ptr below).
+constexpr size_t kSlabScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kSlabScratchBytes];
 
 namespace {
 
@@ -51,6 +60,28 @@ struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
 };
+
+// Device address of `scratch` per device, looked up with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_lookup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 }  // namespace
 
@@ -882,6 +913,13 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     delete pl;
     return dev_fail(e, "hipDeviceGetAttribute");
   }
+  // the static interface-row array of this device (plan creation is the
+  // library's set-up call; the device is current here)
+  e = scratch_lookup(pl->device);
+  if (e != hipSuccess) {
+    delete pl;
+    return dev_fail(e, "hipGetSymbolAddress (interface-row scratch)");
+  }
   const size_t lds_need = cf::ysolve_lds_needed(ny, P, LB, opt.precision == CF_FP64);
   if (lds_need > (size_t)lds_max) {
     delete pl;
@@ -1107,6 +1145,31 @@ cf_status cf_solve_spectral_slabs(cf_plan* pl, int n_slabs, const void* fhat, vo
   if (pl->mixed())
     return slabs_t<float>(pl, n_slabs, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), iface, s);
   return slabs_t<double>(pl, n_slabs, static_cast<const cx<double>*>(fhat), static_cast<cx<double>*>(phat), iface, s);
+}
+
+cf_status cf_solve_spectral_slabs_noalloc(cf_plan* pl, int n_slabs, const void* fhat, void* phat, void* stream) {
+  CF_TRY(check_plan(pl));
+  CF_TRY(check_ptr(fhat, "fhat"));
+  CF_TRY(check_ptr(phat, "phat"));
+  if (pl->opt.flags & CF_PLAN_Y_DCT) return fail(CF_ERR_ARG, "the y-transform solve has no partitions");
+  if (n_slabs < 1 || pl->P % n_slabs != 0)
+    return fail(CF_ERR_ARG, "n_slabs must divide the plan's partition count " + std::to_string(pl->P));
+  const size_t need = (size_t)pl->P * 8 * (size_t)pl->nkx * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
+  if (need > kSlabScratchBytes)
+    return fail(CF_ERR_ARG, "the plan's interface rows need " + std::to_string(need) + " bytes, more than the " +
+                                std::to_string(kSlabScratchBytes) + "-byte static scratch");
+  void* iface = scratch_ptr(pl->device);
+  if (!iface) return fail(CF_ERR_DEVICE, "no interface-row scratch for the plan's device");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // no per-kernel timing here: recording it may create events
+  const bool timing = pl->timing;
+  pl->timing = false;
+  const cf_status st =
+      pl->mixed() ? slabs_t<float>(pl, n_slabs, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), iface, s)
+                  : slabs_t<double>(pl, n_slabs, static_cast<const cx<double>*>(fhat), static_cast<cx<double>*>(phat),
+                                    iface, s);
+  pl->timing = timing;
+  return st;
 }
 
 cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream) {
