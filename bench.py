@@ -29,14 +29,66 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 # are under "also".
 METRIC = "Mpts/s per Poisson solve and per fwd+adjoint step, FP64 vs FP32+refine, % HBM"
 
-# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch; FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, the factors
-# a plain elementwise kernel reading and writing a known size gives on this
-# chip).  Keyed by (kernel, workload); drop an entry when its kernel changes.
-MEASURED_TRAFFIC = {
-    # k_rk2_fused<double, 64, 16, 128>: FETCH_SIZE 1811700 KiB, WRITE_SIZE 3315151 KiB
-    ("rk2_fused", "step550"): (1811700.0 * 2.0 + 3315151.0 * 1.0) * 1024,
+# Model bytes per grid point of the metric's legs (every array each pass must
+# read or write once, at its storage precision; the FP64 forward + adjoint step
+# is the sum over the kernels it launches).
+MODEL_BYTES_PER_POINT = {
+    "poisson_fp64": 80,
+    "poisson_mixed_refine1": 112,
+    "step_fp64": 200,
+    "fwd_adjoint_step_fp64": 568,
+    "fwd_adjoint_step_mixed": 440,
 }
+
+# Source files that define each kernel class (the HBM-traffic counters under
+# profiles/ are keyed to a hash of these files and the compile flags, so a
+# kernel changed since its counters were taken reports no traffic).
+KERNEL_SOURCES = {
+    "rk2_fused": ["cf_common.h", "cf_step_kernels.h", "cf_rk_fused.h", "cf_step_launch.hip"],
+    "correct": ["cf_common.h", "cf_step_kernels.h", "cf_rk_fused.h", "cf_step_launch.hip"],
+    "r2c_x": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
+    "c2r_x": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
+    "fft_z_fwd": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
+    "fft_z_inv": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
+    "ysolve": ["cf_common.h", "cf_pdd.h", "cf_ysolve_kernels.h", "cf_ysolve_launch.hip"],
+}
+
+
+def kernel_source_hash(kernel: str) -> str | None:
+    """sha256 of a kernel class's source files and the flags they are built
+    with (include paths left out)."""
+    import hashlib
+
+    from paper_2104_08863_amd import build as B
+    files = KERNEL_SOURCES.get(kernel)
+    if not files:
+        return None
+    h = hashlib.sha256()
+    for f in files:
+        h.update(f.encode())
+        h.update(open(os.path.join(B.CSRC, f), "rb").read())
+        flags = [a for a in B.HIP_FLAGS + B.EXTRA_FLAGS.get(f, []) if not a.startswith("/")]
+        h.update(" ".join(flags).encode())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the counter summaries
+    in profiles/ (rocprofv3 FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled
+    by the factors a plain copy kernel gives), or None when no summary was taken
+    on the kernel's current source."""
+    import glob
+    want = kernel_source_hash(kernel)
+    for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt")):
+        rec = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+        if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == want:
+            return (float(rec["fetch_kib"]) * float(rec["fetch_factor"])
+                    + float(rec["write_kib"]) * float(rec["write_factor"])) * 1024
+    return None
 
 
 def _pmc_load(base, name):
@@ -157,43 +209,53 @@ def _oracle_rate(call, npts, min_calls=1, max_calls=3, seconds=5.0, warm=True):
     return round(npts / dt / 1e6, 2), n
 
 
-def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
-    """The oracle (plain torch CPU, FP64) on a bounded sample of the workload:
-    the same nx x nz planes and y-grid shape with ny reduced so a few calls fit
-    in the time target; Mpts/s = sample points / wall time per call.  Also: the
-    same sample with one thread, the 64^3 Poisson solve and the 256x128x256
-    projection step (whole grids) with all threads, and the host's cores and
-    CPU model."""
+def cpu_baseline(wl, poisson_only: bool):
+    """The oracle (plain torch CPU, FP64, all host threads) on the workload's
+    own input: one projection step (or Poisson solve) of the full grid, the same
+    seeded arrays the GPU line times (about 20-30 s on 16 host threads).  Also:
+    one thread on a bounded sample of the same recipe (the workload's x-z planes
+    with ny reduced to 16, its own tanh grid; mean of two calls), the 64^3
+    Poisson solve and the 256x128x256 step (whole grids, all threads), and the
+    host's core count and CPU model."""
     import torch
 
     import oracle as O
     from paper_2104_08863_amd import synth
     threads = torch.get_num_threads()
-    budget = 7.0e7 if poisson_only else 8.5e6
-    ny_s = wl.ny
-    while ny_s > 8 and wl.nx * wl.nz * ny_s > budget:
-        ny_s //= 2
-    yf = synth.tanh_faces(ny_s, wl.gamma)
-    box = O.Box(wl.nx, ny_s, wl.nz, wl.lx, wl.lz, yf)
+    yf = wl.y_faces()
+    box = O.Box(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf)
     if poisson_only:
-        f = torch.tensor(synth.uniform_rhs(wl.nx, ny_s, wl.nz, seed=0))
+        f = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0))
         call = lambda: O.poisson(f, box)  # noqa: E731
         what = "Poisson solve (torch CPU FFT + Thomas)"
     else:
-        u, v, w = (torch.tensor(q) for q in synth.perturbed_poiseuille(wl.nx, ny_s, wl.nz, yf, seed=0))
+        u, v, w = (torch.tensor(q) for q in synth.perturbed_poiseuille(wl.nx, wl.ny, wl.nz, yf, seed=0))
         call = lambda: O.projection_step(u, v, w, box, wl.dt, wl.nu, wl.fx)  # noqa: E731
         what = "projection step (RK2 + torch CPU FFT/Thomas Poisson + correction)"
-    npts = wl.nx * ny_s * wl.nz
-    value, n = _oracle_rate(call, npts, seconds=seconds_target / 4)
+    value, n = _oracle_rate(call, wl.npts, max_calls=1, warm=False)
     out = {"value": value, "unit": "Mpts/s", "cores": threads, "kind": "oracle",
-           "sample": f"FP64 oracle {what} on {wl.nx}x{ny_s}x{wl.nz} (the workload's x-z planes, "
-                     f"ny reduced from {wl.ny}), mean of {n} calls"}
+           "sample": f"FP64 oracle {what} on the whole {wl.nx}x{wl.ny}x{wl.nz} input of the GPU line "
+                     f"(same seeded arrays), one call, {threads} threads"}
+    del call
+    if not poisson_only:
+        del u, v, w
+    # one thread on a bounded sample of the same recipe
+    ny_s = 16
+    ys = synth.tanh_faces(ny_s, wl.gamma)
+    bs = O.Box(wl.nx, ny_s, wl.nz, wl.lx, wl.lz, ys)
+    if poisson_only:
+        fs = torch.tensor(synth.uniform_rhs(wl.nx, ny_s, wl.nz, seed=0))
+        cs = lambda: O.poisson(fs, bs)  # noqa: E731
+    else:
+        us, vs, ws = (torch.tensor(q) for q in synth.perturbed_poiseuille(wl.nx, ny_s, wl.nz, ys, seed=0))
+        cs = lambda: O.projection_step(us, vs, ws, bs, wl.dt, wl.nu, wl.fx)  # noqa: E731
     try:
         torch.set_num_threads(1)
-        v1, n1 = _oracle_rate(call, npts, max_calls=1, warm=False)
+        v1, n1 = _oracle_rate(cs, wl.nx * ny_s * wl.nz, min_calls=2, max_calls=2, warm=False)
     finally:
         torch.set_num_threads(threads)
-    out["single_thread"] = {"value": v1, "cores": 1, "calls": n1}
+    out["single_thread"] = {"value": v1, "cores": 1, "calls": n1,
+                            "sample": f"{wl.nx}x{ny_s}x{wl.nz} (the workload's x-z planes, ny reduced to {ny_s})"}
     # whole small grids with all threads
     w1 = synth.WORKLOADS["poisson64"]
     b1 = O.Box(w1.nx, w1.ny, w1.nz, w1.lx, w1.lz, w1.y_faces())
@@ -206,7 +268,26 @@ def cpu_baseline(wl, poisson_only: bool, seconds_target: float = 20.0):
     out["step_fp64_256x128x256"], _ = _oracle_rate(
         lambda: O.projection_step(u4, v4, w4f, b4, w4.dt, w4.nu, w4.fx), w4.nx * w4.ny * w4.nz, max_calls=1)
     out["host"] = _host_info()
+    out["host"]["torch_threads"] = threads
     return out
+
+
+def _progress(what):
+    """One line on stderr per finished figure (the JSON result goes to stdout)."""
+    print(f"bench: {what} done", file=sys.stderr, flush=True)
+
+
+def _leg(name, grid, t, **extra):
+    """Mpts/s and the HBM fraction of one timed figure of the metric, against
+    its model bytes per point."""
+    npts = grid[0] * grid[1] * grid[2]
+    d = {"grid": list(grid), "ms": round(t * 1e3, 4), "Mpts_s": round(npts / t / 1e6, 1)}
+    bpp = MODEL_BYTES_PER_POINT.get(name)
+    if bpp is not None:
+        gbs = bpp * npts / t / 1e9
+        d.update({"model_bytes_per_pt": bpp, "model_GBps": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    d.update(extra)
+    return d
 
 
 def _time(fn, steps, warmup=2):
@@ -341,10 +422,10 @@ def fwd_adjoint_mixed(steps: int = 2, warmup: int = 1):
         pm.projection_step_adjoint(u, v, w, *g, c5.dt, c5.nu, c5.fx, out=g)
     t = _time(fwd_adj5, steps, warmup=warmup)
     finite = bool(torch.isfinite(g[0]).all() and torch.isfinite(o[0]).all())
-    res = {"fwd_adjoint_step_mixed_2048x768x2048": {
-        "grid": [c5.nx, c5.ny, c5.nz], "ms": round(t * 1e3, 2), "Mpts_s": round(n5 / t / 1e6, 1),
-        "finite": finite, "plan_workspace_GB": round(pm.info()["workspace_bytes"] / 1e9, 1),
-        "input": "perturbed Poiseuille (seeded torch CUDA generator), FP32 state"}}
+    res = {"fwd_adjoint_step_mixed_2048x768x2048": _leg(
+        "fwd_adjoint_step_mixed", (c5.nx, c5.ny, c5.nz), t, finite=finite,
+        plan_workspace_GB=round(pm.info()["workspace_bytes"] / 1e9, 1),
+        input="perturbed Poiseuille (seeded torch CUDA generator), FP32 state")}
     del pm, u, v, w, o, g
     torch.cuda.empty_cache()
     return res
@@ -360,22 +441,29 @@ def secondary(wl, steps):
     from paper_2104_08863_amd.api import Plan
     dev = torch.device("cuda", 0)
     res = {}
+    # the 64^3 FP64 Poisson solve (launch-bound: ~20 MB of model traffic)
+    w1 = synth.WORKLOADS["poisson64"]
+    p1 = Plan(w1.nx, w1.ny, w1.nz, w1.lx, w1.lz, w1.y_faces(), precision="fp64")
+    f1 = torch.tensor(synth.uniform_rhs(w1.nx, w1.ny, w1.nz, seed=0), device=dev)
+    o1 = torch.empty_like(f1)
+    t = _time(lambda: p1.poisson_solve(f1, out=o1), 200, warmup=20)
+    res["poisson_fp64_64x64x64"] = _leg("poisson_fp64", (w1.nx, w1.ny, w1.nz), t)
+    _progress("poisson 64^3")
+    del p1, f1, o1
     npts = wl.nx * wl.ny * wl.nz
     yf = wl.y_faces()
     f = torch.tensor(synth.uniform_rhs(wl.nx, wl.ny, wl.nz, seed=0), device=dev)
     p64 = torch.empty_like(f)
     pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="fp64")
     t = _time(lambda: pl.poisson_solve(f, out=p64), steps)
-    res["poisson_fp64"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
-                           "Mpts_s": round(npts / t / 1e6, 1), "model_GBps": round(80 * npts / t / 1e9, 1)}
+    res["poisson_fp64"] = _leg("poisson_fp64", (wl.nx, wl.ny, wl.nz), t)
     del pl
     pm = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, yf, precision="mixed", refine_passes=1)
     pmx = torch.empty_like(f)
     t = _time(lambda: pm.poisson_solve(f, out=pmx), steps)
     err = float(torch.linalg.vector_norm(pmx - p64) / torch.linalg.vector_norm(p64))
-    res["poisson_mixed_refine1"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
-                                    "Mpts_s": round(npts / t / 1e6, 1),
-                                    "rel_l2_vs_fp64_gpu": err}
+    res["poisson_mixed_refine1"] = _leg("poisson_mixed_refine1", (wl.nx, wl.ny, wl.nz), t, rel_l2_vs_fp64_gpu=err)
+    _progress("poisson fp64 / mixed on the step grid")
     del pm, pmx, p64, f
     torch.cuda.empty_cache()
     # uniform y faces: tridiagonal (PDD) path vs the y-transform path
@@ -405,15 +493,16 @@ def secondary(wl, steps):
         pa.projection_step(u, v, w, wl.dt, wl.nu, wl.fx, out=o)
         pa.projection_step_adjoint(u, v, w, *g1, wl.dt, wl.nu, wl.fx, out=go)
     t = _time(fwd_adj, steps)
-    res["fwd_adjoint_step_fp64"] = {"grid": [wl.nx, wl.ny, wl.nz], "ms": round(t * 1e3, 4),
-                                    "Mpts_s": round(npts / t / 1e6, 1)}
+    res["fwd_adjoint_step_fp64"] = _leg("fwd_adjoint_step_fp64", (wl.nx, wl.ny, wl.nz), t)
+    _progress("fwd+adjoint fp64")
     del pa, u, v, w, o, g1, go
     torch.cuda.empty_cache()
     res.update(time_loop_figures(wl, steps))
+    _progress("time loop")
     res.update(rollout_figure(steps))
+    _progress("rollout")
     # mixed-precision Poisson solve on the Re_tau=1000-shaped grid
     big = synth.WORKLOADS["mixed1000"]
-    nb = big.nx * big.ny * big.nz
     pm = Plan(big.nx, big.ny, big.nz, big.lx, big.lz, big.y_faces(), precision="mixed", refine_passes=1)
     vel = synth.powerlaw_velocity_device(big.nx, big.ny, big.nz, seed=0, device=dev)
     fb = pm.divergence(*vel)
@@ -421,14 +510,25 @@ def secondary(wl, steps):
     torch.cuda.empty_cache()
     pb = torch.empty_like(fb)
     t = _time(lambda: pm.poisson_solve(fb, out=pb), max(2, steps // 2), warmup=1)
-    res["poisson_mixed_refine1_2048x512x1536"] = {
-        "grid": [big.nx, big.ny, big.nz], "ms": round(t * 1e3, 3), "Mpts_s": round(nb / t / 1e6, 1),
-        "input": "f = D u of the k^-5/3 power-law field (seed 0, generated on the device)"}
+    res["poisson_mixed_refine1_2048x512x1536"] = _leg(
+        "poisson_mixed_refine1", (big.nx, big.ny, big.nz), t,
+        input="f = D u of the k^-5/3 power-law field (seed 0, generated on the device)")
+    # the same right-hand side solved in FP64 (the metric's FP64 vs FP32+refine)
+    p64 = Plan(big.nx, big.ny, big.nz, big.lx, big.lz, big.y_faces(), precision="fp64")
+    t = _time(lambda: p64.poisson_solve(fb, out=pb), max(2, steps // 2), warmup=1)
+    res["poisson_fp64_2048x512x1536"] = _leg("poisson_fp64", (big.nx, big.ny, big.nz), t)
+    del p64
+    _progress("poisson mixed / fp64 on 2048x512x1536")
     del pm, pb, fb
     torch.cuda.empty_cache()
     res.update(partition_tuning_figures())
+    _progress("partition tuning")
+    res.update(drop_figures(steps))
+    _progress("dropped vs exact y-solve")
     res.update(slab_figures(steps))
+    _progress("y-slab split")
     res.update(fwd_adjoint_mixed(steps=2, warmup=1))
+    _progress("fwd+adjoint mixed 2048x768x2048")
     return res
 
 
@@ -470,6 +570,46 @@ def slab_figures(steps):
     del pl, fh, out, iface
     torch.cuda.empty_cache()
     return res
+
+
+def drop_figures(steps):
+    """The wall-normal solve of the step grid with the default drop tolerance
+    (the dropped reduced system as an outer PDD of 4 groups of 4 partitions on
+    most lines) against the same plan with drop_tol = 0 (exact reduced system on
+    every line): mean y-solve kernel time of each, lines dropped."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    wl = synth.WORKLOADS["step550"]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    res = {}
+    fh = None
+    for tag, tol in (("dropped", -1.0), ("exact", 0.0)):
+        pl = Plan(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces(), precision="fp64", drop_tol=tol)
+        if fh is None:
+            fh = torch.randn(pl.nkx, wl.ny, wl.nz, dtype=torch.complex128, device=dev, generator=gen)
+        out = torch.empty_like(fh)
+        _time(lambda: pl.solve_spectral(fh, out=out), 3)
+        pl.set_timing(True)
+        pl.reset_timing()
+        for _ in range(steps):
+            pl.solve_spectral(fh, out=out)
+        torch.cuda.synchronize()
+        tm = pl.timings()
+        pl.set_timing(False)
+        inf = pl.info()
+        us = 1e3 * tm["ysolve"][0] / tm["ysolve"][1]
+        res[tag] = {"ysolve_us": round(us, 1), "GBps": round(2 * 16 * pl.nkx * wl.ny * wl.nz / (us * 1e-6) / 1e9, 1),
+                    "n_dropped_lines": inf["n_dropped_lines"], "k2_threshold": inf["k2_threshold"]}
+        res["n_lines"] = inf["n_lines"]
+        res["drop_parts"] = inf["drop_parts"]
+        del pl, out
+    del fh
+    torch.cuda.empty_cache()
+    return {"ysolve_drop_vs_exact_fp64_1024x256x512": res}
 
 
 def partition_tuning_figures():
@@ -523,6 +663,8 @@ def main():
     ap.add_argument("--profile-fwd-adjoint-mixed", action="store_true",
                     help="only run two mixed-precision forward + adjoint steps on 2048x768x2048 (for a "
                          "profiler) and exit")
+    ap.add_argument("--source-hash", metavar="KERNEL", help="print the source hash a traffic summary of KERNEL "
+                    "must carry and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain elementwise kernel reading and writing BYTES bytes "
                          "three times (reference for hardware traffic counters) and exit")
@@ -532,6 +674,9 @@ def main():
         return
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace))
+        return
+    if args.source_hash:
+        print(kernel_source_hash(args.source_hash))
         return
     if args.profile_fwd_adjoint_mixed:
         fwd_adjoint_mixed(steps=2, warmup=0)
@@ -609,7 +754,7 @@ def main():
                   for k, v in kern.items()}
     model_bytes = sum(kb(k) * v[1] for k, v in kern.items()) / args.steps
     what = "FP64 pressure-Poisson solve" if args.poisson_only else "FP64 projection step (RK2 + Poisson + correction)"
-    traffic = MEASURED_TRAFFIC.get((dom, wl.name)) if not args.poisson_only else None
+    traffic = measured_traffic(dom, wl.name) if not args.poisson_only else None
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -633,6 +778,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": nbytes},
         "model_GBps_whole_step": round(model_bytes / (ms * 1e-3) / 1e9, 1),
+        "hbm_frac_whole_step": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "measured_copy_GBps": copy_bandwidth(),
         "kernels": per_kernel,
     }
@@ -642,6 +788,7 @@ def main():
         out["also"] = secondary(wl, args.secondary_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.poisson_only)
+        _progress("cpu baseline")
     print(json.dumps(out), flush=True)
 
 

@@ -49,7 +49,7 @@ typedef enum {
   CF_ERR_UNSUPPORTED = 2,  /* sizes outside the supported transform/partition set */
   CF_ERR_NOMEM = 3,        /* device allocation failed at plan creation */
   CF_ERR_DEVICE = 4,       /* a HIP call or launch failed */
-  CF_ERR_NUMERIC = 5       /* non-finite input detected where checked */
+  CF_ERR_NUMERIC = 5       /* non-finite values detected (cf_plan_numeric_status) */
 } cf_status;
 
 enum { CF_FP64 = 0, CF_MIXED = 1 };
@@ -70,6 +70,11 @@ typedef struct {
                          CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS: see below */
   int lines_per_block; /* lines per block of the partitioned solve; 0 = automatic.
                           lines_per_block * n_parts must be <= 512 */
+  int drop_parts;     /* G: the dropped reduced system is an outer PDD of G partitions, each a
+                         group of n_parts/G consecutive partitions solved exactly inside
+                         (Section 2.2 with G partitions); the corner terms of the G-level
+                         Eq. (21) are what drop_tol bounds.  Must divide n_parts.  0 =
+                         automatic: 4 when 4 divides n_parts, else n_parts */
 } cf_options;
 
 /* CF_PLAN_Y_DCT: solve the wall-normal systems by a transform along y instead of
@@ -101,6 +106,10 @@ typedef struct {
   int lines_per_block;    /* lines per block of the partitioned solve */
   size_t slab_iface_bytes; /* device bytes of the interface buffer of cf_solve_spectral_slabs:
                               n_parts * 8 * n_lines values of the plan's precision */
+  int drop_parts;         /* G, the outer partitions of the dropped reduced system */
+  long long n_dropped_lines; /* lines the partitioned solve drops the corner terms for: those
+                              whose block of lines_per_block consecutive lines lies wholly
+                              above k2_threshold (the others take the exact reduced system) */
 } cf_plan_info;
 
 /* Fill *opt with the defaults. */
@@ -271,6 +280,19 @@ cf_status cf_solve_spectral(cf_plan* plan, const void* fhat, void* phat, void* s
  */
 cf_status cf_solve_spectral_slabs(cf_plan* plan, int n_slabs, const void* fhat, void* phat, void* iface,
                                   void* stream);
+
+/*
+ * Failure detection.  Every pressure solve of the partitioned wall-normal solver
+ * (cf_poisson_solve, cf_projection_step, its adjoint, cf_run_steps,
+ * cf_solve_spectral, cf_solve_spectral_slabs) checks the kx = kz = 0 line of its
+ * right-hand side: a non-finite value anywhere in an x-z plane of f (or of the
+ * divergence of u*, i.e. in the velocity state) reaches that plane's entry of
+ * the line (its sum over the plane), and the solve raises a flag in the plan.
+ * This call waits for the work enqueued on `stream` (and the plan's side
+ * stream), returns CF_ERR_NUMERIC if the flag is raised and clears it, else
+ * CF_OK.  Plans with CF_PLAN_Y_DCT do not check.
+ */
+cf_status cf_plan_numeric_status(cf_plan* plan, void* stream);
 
 /*
  * cf_solve_spectral_slabs without the iface argument, for callers that cannot

@@ -25,7 +25,7 @@ CF_PLAN_STEP, CF_PLAN_ADJOINT, CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS = 1, 2, 4, 8
 class cf_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("n_parts", C.c_int), ("drop_tol", C.c_double),
                 ("fp64_kx", C.c_int), ("fp64_kz", C.c_int), ("refine_passes", C.c_int),
-                ("flags", C.c_int), ("lines_per_block", C.c_int)]
+                ("flags", C.c_int), ("lines_per_block", C.c_int), ("drop_parts", C.c_int)]
 
 
 class cf_plan_info(C.Structure):
@@ -33,7 +33,7 @@ class cf_plan_info(C.Structure):
                 ("n_parts", C.c_int), ("rows_per_part", C.c_int), ("n_lines", C.c_longlong),
                 ("n_drop_lines", C.c_longlong), ("n_special", C.c_longlong),
                 ("k2_threshold", C.c_double), ("workspace_bytes", C.c_size_t), ("lines_per_block", C.c_int),
-                ("slab_iface_bytes", C.c_size_t)]
+                ("slab_iface_bytes", C.c_size_t), ("drop_parts", C.c_int), ("n_dropped_lines", C.c_longlong)]
 
 
 _P = C.c_void_p
@@ -60,6 +60,7 @@ SIGNATURES = {
     "cf_solve_spectral": (_I, [_P, _P, _P, _P]),
     "cf_solve_spectral_slabs": (_I, [_P, _I, _P, _P, _P, _P]),
     "cf_solve_spectral_slabs_noalloc": (_I, [_P, _I, _P, _P, _P]),
+    "cf_plan_numeric_status": (_I, [_P, _P]),
     "cf_plan_set_timing": (_I, [_P, _I]),
     "cf_plan_reset_timing": (_I, [_P]),
     "cf_plan_get_timing": (_I, [_P, _I, C.POINTER(_D), C.POINTER(C.c_longlong)]),
@@ -73,6 +74,7 @@ HOST_SIGNATURES = {
     "cfh_rfft": (_I, [_I, _I, _P, _P]),
     "cfh_irfft": (_I, [_I, _I, _P, _P]),
     "cfh_pdd_line": (_I, [_I, _I, _P, _P, _D, _I, _I, _P, _P]),
+    "cfh_pdd_line_grouped": (_I, [_I, _I, _I, _P, _P, _D, _I, _P, _P]),
 }
 
 _lib = None

@@ -24,13 +24,15 @@ class Plan:
     'pdd' (partitioned tridiagonal solve) or 'dct' (transform along y; uniform
     faces and FP64 only).  n_parts / lines_per_block: partitions per line and
     lines per block of the partitioned solve (0: automatic); tune_parts: choose
-    both by timing every admissible pair at creation (see partition_timings)."""
+    both by timing every admissible pair at creation (see partition_timings).
+    drop_parts: outer partitions G of the dropped reduced system (groups of
+    n_parts/G partitions, exact inside; 0: automatic).  drop_tol < 0: default."""
 
     def __init__(self, nx: int, ny: int, nz: int, lx: float, lz: float, y_faces,
                  precision: str = "fp64", n_parts: int = 0, drop_tol: float = -1.0,
                  fp64_kx: int = 4, fp64_kz: int = 4, refine_passes: int = 1,
                  step: bool = False, adjoint: bool = False, y_solver: str = "pdd",
-                 lines_per_block: int = 0, tune_parts: bool = False, device=None):
+                 lines_per_block: int = 0, tune_parts: bool = False, drop_parts: int = 0, device=None):
         lib = L.lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.nkx = self.nx // 2 + 1
@@ -51,6 +53,7 @@ class Plan:
         opt.fp64_kz = int(fp64_kz)
         opt.refine_passes = int(refine_passes)
         opt.lines_per_block = int(lines_per_block)
+        opt.drop_parts = int(drop_parts)
         if y_solver not in ("pdd", "dct"):
             raise ValueError("y_solver must be 'pdd' or 'dct'")
         opt.flags = (L.CF_PLAN_STEP if (step or adjoint) else 0) | (L.CF_PLAN_ADJOINT if adjoint else 0) \
@@ -94,6 +97,15 @@ class Plan:
         return [(parts[q], lbs[q], us[q]) for q in range(cnt)]
 
     # ------------------------------------------------------------------ timing
+    def numeric_status(self) -> bool:
+        """Waits for the current stream; True when no pressure solve since the
+        last call saw a non-finite right-hand side (the check is cleared)."""
+        st = L.lib().cf_plan_numeric_status(self._h, _stream())
+        if st == L.CF_ERR_NUMERIC:
+            return False
+        L.check(st, "cf_plan_numeric_status")
+        return True
+
     def set_timing(self, enable: bool):
         L.check(L.lib().cf_plan_set_timing(self._h, int(bool(enable))), "cf_plan_set_timing")
 

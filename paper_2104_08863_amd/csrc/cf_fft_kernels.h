@@ -70,6 +70,12 @@ __device__ __forceinline__ void fft_passes(cx<T>* x, int t, cx<T>* sl, const cx<
   if constexpr (PASS + 1 < P.np) fft_passes<N, INV, T, PASS + 1>(x, t, sl, tw);
 }
 
+constexpr int pow2_floor(int n) {
+  int p = 1;
+  while (2 * p <= n) p *= 2;
+  return p;
+}
+
 constexpr int lds_lines(int n, int tpl, int esize, int budget) {
   int l = 256 / tpl;
   if (l < 1) l = 1;
@@ -132,8 +138,11 @@ struct XCfg {
 
 // Row sources for the forward real transform: element pair (x_{2m}, x_{2m+1})
 // of row (j, k).
+// Sources whose kPSum is true also give the FP64 sum over their rows of the
+// pressure they read (psum_pair); k_r2c_x adds it up per block into psum.
 template <typename T, typename Tin>
 struct SrcPlain {
+  static constexpr bool kPSum = false;
   const Tin* __restrict__ f;
   int nx, nz;
   __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
@@ -148,6 +157,7 @@ struct SrcPlain {
 // + (w_k - w_{k-1})/dz] * scale with v = 0 on both walls.
 template <typename T, typename Ts>
 struct SrcDiv {
+  static constexpr bool kPSum = false;
   const Ts* __restrict__ u;
   const Ts* __restrict__ v;
   const Ts* __restrict__ w;
@@ -189,6 +199,7 @@ struct SrcDiv {
 // hand side of the transposed projection (g / W with the face weights W).
 template <typename T, typename Ts>
 struct SrcDivW {
+  static constexpr bool kPSum = false;
   const Ts* __restrict__ u;
   const Ts* __restrict__ v;
   const Ts* __restrict__ w;
@@ -228,15 +239,24 @@ struct SrcDivW {
 // FP64 residual of the Poisson equation, r = f - L_h p (7-point staggered
 // Laplacian, no flux through the walls: a_0 = c_{ny-1} = 0), rounded to T.
 // The right-hand side f comes from an inner source evaluated in FP64 (a plain
-// array, a divergence, or a weighted divergence).
+// array, a divergence, or a weighted divergence).  The residual cannot see a
+// constant in p, so the kernel also sums p (FP64, per block of rows) into
+// psum: the correction solve uses it to restore the gauge mean_W(p) = 0 that
+// the FP32 transforms of the previous solve leave off by their rounding.
 template <typename T, typename In>
 struct SrcResidual {
+  static constexpr bool kPSum = true;
   In in;
   const double* __restrict__ p;
   const double* __restrict__ a;
   const double* __restrict__ c;
   double rdx2, rdz2;
   int nx, ny, nz;
+  double* __restrict__ psum;  // [blocks of k_r2c_x]: the block's sum of p
+  __device__ __forceinline__ double psum_pair(int j, int k, int m) const {
+    const cx<double> pc = reinterpret_cast<const cx<double>*>(p + ((long)j * nz + k) * nx)[m];
+    return pc.re + pc.im;
+  }
   __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
     const long plane = (long)nz * nx;
     const long row = ((long)j * nz + k) * nx;
@@ -282,11 +302,15 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const c
   const int k = k0 + rr;
   const bool ok = k < nz;
   cx<T> x[F::E];
+  double psum = 0.0;
 #pragma unroll
   for (int q = 0; q < F::E / F::R0; ++q) {
     const int b = tl + q * F::TPL;
 #pragma unroll
-    for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? src.pair(j, k, st_in(NH, F::R0, b, r)) : mk(T(0), T(0));
+    for (int r = 0; r < F::R0; ++r) {
+      x[q * F::R0 + r] = ok ? src.pair(j, k, st_in(NH, F::R0, b, r)) : mk(T(0), T(0));
+      if constexpr (Src::kPSum) psum += ok ? src.psum_pair(j, k, st_in(NH, F::R0, b, r)) : 0.0;
+    }
   }
   cx<T>* sl = lds + rr * S;
   fft_passes<NH, false, T, 0>(x, tl, sl, tw);
@@ -311,6 +335,20 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const c
       cx<T> X = r2c_post(row[lpad(kx == NH ? 0 : kx)], row[lpad(kx == 0 ? 0 : NH - kx)], twp[kx]);
       spec[(plane + kx) * nz + k0 + r] = X;
     }
+  }
+  if constexpr (Src::kPSum) {
+    // block sum of p in a fixed order (the LDS tile is free again: TH <= K*S
+    // complex slots hold TH doubles)
+    double* red = reinterpret_cast<double*>(lds);
+    __syncthreads();
+    red[threadIdx.x] = psum;
+    __syncthreads();
+    constexpr int P2 = pow2_floor(TH);
+    for (int h = P2; h > 0; h >>= 1) {
+      if (threadIdx.x < h && threadIdx.x + h < TH) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) src.psum[blockIdx.x] = red[0];
   }
 }
 

@@ -88,11 +88,26 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
   }
 }
 
+template <typename T>
+int r2c_rows(int nh) {
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return XCfg<T, N>::K;
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return 0;
+  }
+}
+template int r2c_rows<double>(int);
+template int r2c_rows<float>(int);
+
 template <typename T, typename In>
 static hipError_t r2c_resid_any(int nh, In in, const double* p, const double* a, const double* c, double rdx,
                                 double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
-                                hipStream_t s) {
-  SrcResidual<T, In> src{in, p, a, c, rdx * rdx, rdz * rdz, 2 * nh, ny, nz};
+                                double* psum, hipStream_t s) {
+  SrcResidual<T, In> src{in, p, a, c, rdx * rdx, rdz * rdz, 2 * nh, ny, nz, psum};
   switch (nh) {
 #define CF_CASE(N) \
   case N:          \
@@ -108,15 +123,16 @@ template <typename T, typename Ts>
 hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
                             double scale, const double* p, const double* a, const double* c, const double* rdy,
                             const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
-                            const cx<T>* twp, int ny, int nz, hipStream_t s) {
+                            const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s) {
   const int nx = 2 * nh;
   if (kind == 0)
-    return r2c_resid_any<T>(nh, SrcPlain<double, double>{f, nx, nz}, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, s);
+    return r2c_resid_any<T>(nh, SrcPlain<double, double>{f, nx, nz}, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, psum,
+                            s);
   if (kind == 1)
     return r2c_resid_any<T>(nh, SrcDiv<double, Ts>{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz}, p, a, c, rdx, rdz,
-                            spec, tw, twp, ny, nz, s);
+                            spec, tw, twp, ny, nz, psum, s);
   return r2c_resid_any<T>(nh, SrcDivW<double, Ts>{u, v, w, rdy, rdyc, rdx, rdz, nx, ny, nz}, p, a, c, rdx, rdz,
-                          spec, tw, twp, ny, nz, s);
+                          spec, tw, twp, ny, nz, psum, s);
 }
 
 template <typename T, typename Ts>
@@ -199,7 +215,7 @@ template hipError_t launch_r2c_resid<float, float>(int, int, const double*, cons
                                                    const float*, double, const double*, const double*,
                                                    const double*, const double*, const double*, double, double,
                                                    cx<float>*, const cx<float>*, const cx<float>*, int, int,
-                                                   hipStream_t);
+                                                   double*, hipStream_t);
 template hipError_t launch_r2c_divw<float, float>(int, const float*, const float*, const float*, const double*,
                                                   const double*, double, double, cx<float>*, const cx<float>*,
                                                   const cx<float>*, int, int, hipStream_t);

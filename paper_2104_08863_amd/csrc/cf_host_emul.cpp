@@ -142,6 +142,88 @@ void pdd_line_m(int P, const T* a, const T* c, T k2, int exact, std::vector<cx<T
   }
 }
 
+// The dropped reduced system as an outer PDD of G groups of Pg = P/G inner
+// partitions, in the order of the y kernel: inner interfaces of each group by
+// cyclic reduction with the three right-hand sides, the groups' end values, the
+// dropped 2x2 step on the outer interfaces, and the correction with the
+// effective interface values.
+template <int M, typename T>
+void pdd_line_grouped_m(int P, int G, const T* a, const T* c, T k2, std::vector<cx<T>>& d) {
+  std::vector<std::vector<T>> v(P, std::vector<T>(M)), w(P, std::vector<T>(M));
+  for (int i = 0; i < P; ++i) cf::pdd_local<M, T>(a + i * M, c + i * M, k2, d.data() + i * M, v[i].data(), w[i].data());
+  const int Pg = P / G;
+  const cx<T> z0 = mk(T(0), T(0));
+  std::vector<cx<T>> y1(P, z0), y2(P, z0);
+  std::vector<T> y1v(P, T(0)), y2v(P, T(0)), y1w(P, T(0)), y2w(P, T(0));
+  for (int g = 0; g < G; ++g) {
+    const int sf = g * Pg, sl = sf + Pg - 1;
+    std::vector<cf::zrow3<T>> z(P), zn(P);
+    for (int i = sf; i < sl; ++i) {
+      z[i].z = cf::zrow_make(v[i][M - 1], w[i][M - 1], v[i + 1][0], w[i + 1][0], d[i * M + M - 1], d[(i + 1) * M]);
+      z[i].rv0 = (i == sf) ? v[i][M - 1] : T(0);
+      z[i].rv1 = T(0);
+      z[i].rw0 = T(0);
+      z[i].rw1 = (i + 1 == sl) ? w[i + 1][0] : T(0);
+    }
+    for (int st = 1; st < Pg - 1; st *= 2) {
+      for (int i = sf; i < sl; ++i) {
+        const bool hl = i - st >= sf, hh = i + st < sl;
+        zn[i] = cf::zrow3_reduce(z[i], &z[hl ? i - st : i], hl, &z[hh ? i + st : i], hh);
+      }
+      for (int i = sf; i < sl; ++i) z[i] = zn[i];
+    }
+    for (int i = sf; i < sl; ++i) cf::zrow3_finish(z[i], y1[i], y2[i], y1v[i], y2v[i], y1w[i], y2w[i]);
+  }
+  std::vector<cx<T>> gxm(G), gx1(G), Y1(G, z0), Y2(G, z0);
+  std::vector<T> gwm(G), gv1(G);
+  for (int g = 0; g < G; ++g) {
+    const int sf = g * Pg, sl = sf + Pg - 1;
+    const cx<T> y1p = sl > sf ? y1[sl - 1] : z0;
+    const T y1wp = sl > sf ? y1w[sl - 1] : T(0);
+    gxm[g] = d[sl * M + M - 1] - y1p * v[sl][M - 1];
+    gwm[g] = w[sl][M - 1] - v[sl][M - 1] * y1wp;
+    gx1[g] = d[sf * M] - y2[sf] * w[sf][0];
+    gv1[g] = v[sf][0] - w[sf][0] * y2v[sf];
+  }
+  for (int g = 0; g + 1 < G; ++g) cf::pdd_cramer(gwm[g], gv1[g + 1], gxm[g], gx1[g + 1], Y1[g], Y2[g]);
+  for (int i = 0; i < P; ++i) {
+    const int g = i / Pg, sf = g * Pg, sl = sf + Pg - 1;
+    const cx<T> Y1p = g > 0 ? Y1[g - 1] : z0;
+    const cx<T> Y2n = g + 1 < G ? Y2[g] : z0;
+    const bool prev_in = i > sf;
+    const cx<T> y1i = prev_in ? y1[i - 1] : z0;
+    const T y1vi = prev_in ? y1v[i - 1] : T(0), y1wi = prev_in ? y1w[i - 1] : T(0);
+    const cx<T> y1eff = y1i + Y1p * ((i == sf ? T(1) : T(0)) - y1vi) - Y2n * y1wi;
+    const cx<T> y2eff = y2[i] - Y1p * y2v[i] + Y2n * ((i == sl ? T(1) : T(0)) - y2w[i]);
+    cf::pdd_correct<M, T>(d.data() + i * M, v[i].data(), w[i].data(), y1eff, y2eff);
+  }
+}
+
+template <typename T>
+int pdd_line_grouped(int ny, int P, int G, const double* a, const double* c, double k2, const double* din,
+                     double* xout) {
+  if (P < 1 || ny % P || G < 1 || P % G) return 1;
+  const int M = ny / P;
+  std::vector<T> at(a, a + ny), ct(c, c + ny);
+  std::vector<cx<T>> d(ny);
+  for (int j = 0; j < ny; ++j) d[j] = mk((T)din[2 * j], (T)din[2 * j + 1]);
+  switch (M) {
+#define CF_CASE(MM)                                                         \
+  case MM:                                                                  \
+    pdd_line_grouped_m<MM, T>(P, G, at.data(), ct.data(), (T)k2, d);        \
+    break;
+    CF_CASE(1) CF_CASE(2) CF_CASE(3) CF_CASE(4) CF_CASE(6) CF_CASE(8) CF_CASE(12) CF_CASE(16)
+#undef CF_CASE
+    default:
+      return 2;
+  }
+  for (int j = 0; j < ny; ++j) {
+    xout[2 * j] = d[j].re;
+    xout[2 * j + 1] = d[j].im;
+  }
+  return 0;
+}
+
 template <typename T>
 int pdd_line(int ny, int P, const double* a, const double* c, double k2, int exact, const double* din,
              double* xout) {
@@ -193,6 +275,13 @@ int cfh_irfft(int nx, int fp32, const double* X, double* x) {
 int cfh_pdd_line(int ny, int P, const double* a, const double* c, double k2, int exact, int fp32,
                  const double* d, double* x) {
   return fp32 ? pdd_line<float>(ny, P, a, c, k2, exact, d, x) : pdd_line<double>(ny, P, a, c, k2, exact, d, x);
+}
+
+// The same line with the dropped reduced system taken as an outer PDD of G
+// groups of P/G partitions (exact inside each group).
+int cfh_pdd_line_grouped(int ny, int P, int G, const double* a, const double* c, double k2, int fp32,
+                         const double* d, double* x) {
+  return fp32 ? pdd_line_grouped<float>(ny, P, G, a, c, k2, d, x) : pdd_line_grouped<double>(ny, P, G, a, c, k2, d, x);
 }
 
 }

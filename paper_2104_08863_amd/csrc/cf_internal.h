@@ -30,11 +30,17 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
 
 // Forward real transform of the FP64 residual f - L_h p with f = the array f
 // (kind 0), scale * D(u, v, w) (kind 1) or D(u / W, v / W, w / W) (kind 2).
+// psum: one double per block, the block's FP64 sum of p; block (j, b) covers
+// rows k = b*K .. b*K+K-1 of plane j and is entry j * ceil(nz/K) + b, with K =
+// r2c_rows<T>(nh).
 template <typename T, typename Ts>
 hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
                             double scale, const double* p, const double* a, const double* c, const double* rdy,
                             const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
-                            const cx<T>* twp, int ny, int nz, hipStream_t s);
+                            const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s);
+// Rows per block of the x transforms of half-length nh.
+template <typename T>
+int r2c_rows(int nh);
 
 // Divergence fused into the forward real transform, velocity type Ts.
 template <typename T, typename Ts>
@@ -79,6 +85,13 @@ struct YLaunch {
   int mode = 0;            // YMode: whole lines, or one y-slab's local / finishing pass
   int pa = 0, pb = 0;      // slab modes: partitions [pa, pb)
   void* iface = nullptr;   // slab modes: interface rows [P][8][nlines] of the plan's precision
+  int G = 0;               // outer partitions of the dropped reduced system (0: P)
+  // LB-line blocks solved with the exact (blocks_exact: null = all blocks) and
+  // the dropped reduced system (blocks_drop: null = none); device arrays
+  const int* blocks_exact = nullptr;
+  long n_exact = 0;
+  const int* blocks_drop = nullptr;
+  long n_drop = 0;
 };
 
 // Default lines per block of the partitioned solve for P partitions.
@@ -88,14 +101,18 @@ size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64);
 
 template <typename T>
 hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,
-                         const T* kx2, const T* kz2, T k2drop, hipStream_t s);
+                         const T* kx2, const T* kz2, hipStream_t s);
 
 // Whole-line FP64 Thomas on the listed lines of layout B, with per-line
-// elimination factors den, cp ([n_lines][ny]) prepared by the plan.
+// elimination factors den, cp ([n_lines][ny]) prepared by the plan.  psum
+// (nullable): [ny][nzb] block sums of a pressure p; when given, the kx = kz = 0
+// line is gauged to the dy-weighted mean -mean_W(p) * nx * nz instead of 0, so
+// that adding the solution to p makes mean_W vanish.  numflag (nullable): set
+// to 1 when the kx = kz = 0 line of fin holds a non-finite value.
 template <typename T>
 hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* den,
                                 const double* cp, const double* dy, const int* lines, int n_lines,
-                                int ny, int nz, hipStream_t s);
+                                int ny, int nz, const double* psum, int nzb, int* numflag, hipStream_t s);
 
 bool ysolve_m_compiled(int m, bool fp64);
 

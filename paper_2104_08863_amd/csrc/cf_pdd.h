@@ -166,6 +166,106 @@ CF_HD void zrow_finish(const zrow<T>& z, cx<T>& y1, cx<T>& y2) {
   m22_mv(m22_inv(z.D), z.r0, z.r1, y1, y2);
 }
 
+// Reduced-system rows carrying two more (real) right-hand sides next to the
+// complex one: the two-level solve (a group of consecutive partitions solved
+// exactly as one partition of an outer PDD) needs, besides the group's own
+// solution, its two spike columns, whose partition-level right-hand sides are
+// the first partition's v and the last partition's w.  The matrix part is
+// reduced once for all three.
+template <typename T>
+struct zrow3 {
+  zrow<T> z;
+  T rv0, rv1, rw0, rw1;
+};
+
+// SoA storage of zrow3 (20 planes of n values; planes 0..15 as zrow_soa).
+template <typename T>
+struct zrow3_soa {
+  T* base;
+  int n;
+  CF_HD void put(int k, const zrow3<T>& z) const {
+    zrow_soa<T>{base, n}.put(k, z.z);
+    T* p = base + 16 * n + k;
+    p[0] = z.rv0;
+    p[n] = z.rv1;
+    p[2 * n] = z.rw0;
+    p[3 * n] = z.rw1;
+  }
+  CF_HD zrow3<T> get(int k) const {
+    zrow3<T> z;
+    z.z = zrow_soa<T>{base, n}.get(k);
+    const T* p = base + 16 * n + k;
+    z.rv0 = p[0];
+    z.rv1 = p[n];
+    z.rw0 = p[2 * n];
+    z.rw1 = p[3 * n];
+    return z;
+  }
+};
+
+template <typename T>
+CF_HD void m22_mvr(m22<T> m, T u0, T u1, T& o0, T& o1) {
+  o0 = m.a * u0 + m.b * u1;
+  o1 = m.c * u0 + m.d * u1;
+}
+
+// zrow_reduce with the two real right-hand sides carried along.
+template <typename T>
+CF_HD zrow3<T> zrow3_reduce(const zrow3<T>& me, const zrow3<T>* lo, bool has_lo, const zrow3<T>* hi,
+                            bool has_hi) {
+  zrow3<T> o;
+  o.z.D = me.z.D;
+  o.z.r0 = me.z.r0;
+  o.z.r1 = me.z.r1;
+  o.rv0 = me.rv0;
+  o.rv1 = me.rv1;
+  o.rw0 = me.rw0;
+  o.rw1 = me.rw1;
+  o.z.L = m22<T>{T(0), T(0), T(0), T(0)};
+  o.z.U = m22<T>{T(0), T(0), T(0), T(0)};
+  if (has_lo) {
+    const m22<T> al = m22_neg(m22_mul(me.z.L, m22_inv(lo->z.D)));
+    o.z.L = m22_mul(al, lo->z.L);
+    o.z.D = m22_add(o.z.D, m22_mul(al, lo->z.U));
+    cx<T> t0, t1;
+    m22_mv(al, lo->z.r0, lo->z.r1, t0, t1);
+    o.z.r0 = o.z.r0 + t0;
+    o.z.r1 = o.z.r1 + t1;
+    T s0, s1;
+    m22_mvr(al, lo->rv0, lo->rv1, s0, s1);
+    o.rv0 += s0;
+    o.rv1 += s1;
+    m22_mvr(al, lo->rw0, lo->rw1, s0, s1);
+    o.rw0 += s0;
+    o.rw1 += s1;
+  }
+  if (has_hi) {
+    const m22<T> be = m22_neg(m22_mul(me.z.U, m22_inv(hi->z.D)));
+    o.z.U = m22_mul(be, hi->z.U);
+    o.z.D = m22_add(o.z.D, m22_mul(be, hi->z.L));
+    cx<T> t0, t1;
+    m22_mv(be, hi->z.r0, hi->z.r1, t0, t1);
+    o.z.r0 = o.z.r0 + t0;
+    o.z.r1 = o.z.r1 + t1;
+    T s0, s1;
+    m22_mvr(be, hi->rv0, hi->rv1, s0, s1);
+    o.rv0 += s0;
+    o.rv1 += s1;
+    m22_mvr(be, hi->rw0, hi->rw1, s0, s1);
+    o.rw0 += s0;
+    o.rw1 += s1;
+  }
+  return o;
+}
+
+template <typename T>
+CF_HD void zrow3_finish(const zrow3<T>& z, cx<T>& y1, cx<T>& y2, T& y1v, T& y2v, T& y1w, T& y2w) {
+  const m22<T> inv = m22_inv(z.z.D);
+  m22_mv(inv, z.z.r0, z.z.r1, y1, y2);
+  m22_mvr(inv, z.rv0, z.rv1, y1v, y2v);
+  m22_mvr(inv, z.rw0, z.rw1, y1w, y2w);
+}
+
 // Step 5.
 template <int M, typename T>
 CF_HD void pdd_correct(cx<T>* x, const T* v, const T* w, cx<T> y1prev, cx<T> y2) {

@@ -48,6 +48,12 @@ cf_status dev_fail(hipError_t e, const char* what) {
   return CF_ERR_DEVICE;
 }
 
+#define CF_HIP_RET(x)                              \
+  do {                                             \
+    hipError_t _e = (x);                           \
+    if (_e != hipSuccess) return dev_fail(_e, #x); \
+  } while (0)
+
 // exp(-2 pi i m / n) from the exactly reduced ratio m/n.
 cx<double> unit_root(long m, long n) {
   m %= n;
@@ -92,8 +98,15 @@ struct cf_plan {
   int device;
   int P, M;
   int LB;  // lines per block of the partitioned solve
+  int G;   // outer partitions of the dropped reduced system
   double k2drop;
-  long long n_drop;
+  long long n_drop;     // lines above the drop threshold
+  long long n_dropped;  // lines in blocks wholly above it (dropped by the kernel)
+  // LB-line blocks of the partitioned solve taking the exact and the dropped
+  // reduced system (host lists; the device copy d_blocks holds the exact list
+  // then the dropped one)
+  std::vector<int> blocks_exact, blocks_drop;
+  int* d_blocks = nullptr;
   // partition counts and block shapes timed at creation (CF_PLAN_TUNE_PARTS)
   struct TuneRow {
     int P, LB;
@@ -131,6 +144,13 @@ struct cf_plan {
   double* d_stat_part = nullptr;
   int stat_nch = 1;
   double* fws = nullptr;  // mixed precision: copy of f when p aliases it
+  // mixed precision: FP64 block sums of p from the residual transform (gauge
+  // of the correction solves), [ny][psum_nzb]
+  double* d_psum = nullptr;
+  int psum_nzb = 0;
+  // set by the kx = kz = 0 line solve when its right-hand side holds a
+  // non-finite value; read and cleared by cf_plan_numeric_status
+  int* d_numflag = nullptr;
   // adjoint workspace: projected gradient g* and gb (state precision)
   void *gsu = nullptr, *gsv = nullptr, *gsw = nullptr, *gbu = nullptr, *gbv = nullptr, *gbw = nullptr;
   double *d_dyc = nullptr;
@@ -265,46 +285,57 @@ cf_status harvest(cf_plan* pl) {
   return CF_OK;
 }
 
-// Largest corner term of Eq. (21) over the interior partitions, for one k^2.
+// Largest corner term of Eq. (21) over the interior partitions of the outer
+// (G-partition) PDD, for one k^2: partition g of ny/G rows solves A_g v =
+// a_first e_1 and A_g w = c_last e_last (Thomas, FP64), and the corner terms are
+// v at its last row and w at its first.
 double corner_delta(const cf_plan* pl, double k2) {
-  const int P = pl->P, M = pl->M;
+  const int G = pl->G, Mg = pl->ny / G;
   double delta = 0.0;
-  std::vector<cx<double>> d(M);
-  std::vector<double> v(M), w(M);
-  for (int i = 1; i + 1 < P; ++i) {
-    std::fill(d.begin(), d.end(), cf::mk(0.0, 0.0));
-    const double* ar = pl->a.data() + i * M;
-    const double* cr = pl->c.data() + i * M;
-    switch (M) {
-#define CF_CASE(MM) \
-  case MM:          \
-    cf::pdd_local<MM, double>(ar, cr, k2, d.data(), v.data(), w.data()); \
-    break;
-      CF_CASE(1) CF_CASE(2) CF_CASE(3) CF_CASE(4) CF_CASE(6) CF_CASE(8) CF_CASE(12) CF_CASE(16) CF_CASE(24)
-      CF_CASE(32)
-#undef CF_CASE
-      default:
-        return INFINITY;
+  std::vector<double> cp(Mg), v(Mg), w(Mg);
+  for (int g = 1; g + 1 < G; ++g) {
+    const double* ar = pl->a.data() + g * Mg;
+    const double* cr = pl->c.data() + g * Mg;
+    // forward elimination of the block (its first a and last c left out)
+    double den_last = 0.0;
+    for (int s = 0; s < Mg; ++s) {
+      const double b = -(ar[s] + cr[s]) - k2;
+      const double den = (s == 0) ? b : b - ar[s] * cp[s - 1];
+      cp[s] = (s == Mg - 1) ? 0.0 : cr[s] / den;
+      v[s] = (s == 0) ? ar[0] / den : -(ar[s] * v[s - 1]) / den;
+      if (s == Mg - 1) den_last = den;
     }
-    delta = std::max(delta, std::max(std::fabs(v[M - 1]), std::fabs(w[0])));
+    w[Mg - 1] = cr[Mg - 1] / den_last;
+    for (int s = Mg - 2; s >= 0; --s) {
+      v[s] = v[s] - cp[s] * v[s + 1];
+      w[s] = -(cp[s] * w[s + 1]);
+    }
+    delta = std::max(delta, std::max(std::fabs(v[Mg - 1]), std::fabs(w[0])));
   }
   return delta;
 }
 
+// Default outer partitions of the dropped reduced system: four groups when
+// four divide P (the corner terms then span a quarter of the channel, long
+// enough on the stretched workload grids for most wavenumbers), else P.
+int auto_drop_parts(int P) { return (P % 4 == 0) ? 4 : P; }
+
 // Partitioning of the wall-normal lines into P parts of M = ny/P rows (Section
-// 2.2) and the drop threshold that goes with it: the smallest k^2 whose corner
-// terms are all <= drop_tol (the corner terms fall monotonically with k^2).
+// 2.2), the outer partitions G of the dropped reduced system, and the drop
+// threshold that goes with them: the smallest k^2 whose G-level corner terms
+// are all <= drop_tol (the corner terms fall monotonically with k^2).
 void set_partitions(cf_plan* pl, int P, int LB) {
   pl->P = P;
   pl->M = pl->ny / P;
   pl->LB = LB;
+  pl->G = (pl->opt.drop_parts > 0 && P % pl->opt.drop_parts == 0) ? pl->opt.drop_parts : auto_drop_parts(P);
   double kmax = 0.0;
   for (double v : pl->kx2) kmax = std::max(kmax, v);
   double kzm = 0.0;
   for (double v : pl->kz2) kzm = std::max(kzm, v);
   kmax += kzm;
   const double tol = pl->opt.drop_tol;
-  if (P <= 2) {
+  if (pl->G <= 2) {
     pl->k2drop = 0.0;
   } else if (corner_delta(pl, kmax) > tol) {
     pl->k2drop = INFINITY;
@@ -321,6 +352,32 @@ void set_partitions(cf_plan* pl, int P, int LB) {
   for (int kx = 0; kx < pl->nkx; ++kx)
     for (int kz = 0; kz < pl->nz; ++kz)
       if (pl->kx2[kx] + pl->kz2[kz] >= pl->k2drop) ++pl->n_drop;
+  // a block of LB consecutive lines drops the corner terms only when all of
+  // its lines qualify
+  const long nl = (long)pl->nkx * pl->nz;
+  pl->n_dropped = 0;
+  pl->blocks_exact.clear();
+  pl->blocks_drop.clear();
+  for (long b0 = 0; b0 < nl; b0 += LB) {
+    const long b1 = std::min(nl, b0 + LB);
+    bool all = true;
+    for (long l = b0; l < b1 && all; ++l) all = pl->kx2[l / pl->nz] + pl->kz2[l % pl->nz] >= pl->k2drop;
+    if (all) {
+      pl->n_dropped += b1 - b0;
+      pl->blocks_drop.push_back(int(b0 / LB));
+    } else {
+      pl->blocks_exact.push_back(int(b0 / LB));
+    }
+  }
+}
+
+// Copies the block lists of set_partitions to the device (synchronously).
+cf_status upload_blocks(cf_plan* pl) {
+  if (!pl->d_blocks) return CF_OK;
+  const size_t ne = pl->blocks_exact.size(), nd = pl->blocks_drop.size();
+  if (ne) CF_HIP_RET(hipMemcpy(pl->d_blocks, pl->blocks_exact.data(), ne * sizeof(int), hipMemcpyHostToDevice));
+  if (nd) CF_HIP_RET(hipMemcpy(pl->d_blocks + ne, pl->blocks_drop.data(), nd * sizeof(int), hipMemcpyHostToDevice));
+  return CF_OK;
 }
 
 int auto_parts(int ny, bool fp64) {
@@ -457,8 +514,14 @@ hipError_t pdd_launch(const cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStrea
   y.pa = pa;
   y.pb = pb;
   y.iface = iface;
-  const T k2drop = std::isfinite(pl->k2drop) ? T(pl->k2drop) : T(INFINITY);
-  return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), k2drop, s);
+  y.G = pl->G;
+  if (pl->d_blocks) {
+    y.blocks_exact = pl->d_blocks;
+    y.n_exact = (long)pl->blocks_exact.size();
+    y.blocks_drop = pl->blocks_drop.empty() ? nullptr : pl->d_blocks + pl->blocks_exact.size();
+    y.n_drop = (long)pl->blocks_drop.size();
+  }
+  return cf::launch_ysolve<T>(y, fin, pout, TB::a(pl), TB::c(pl), TB::kx2(pl), TB::kz2(pl), s);
 }
 
 // The partitioned solve as n_slabs y-slabs: every slab's local pass, then the
@@ -476,7 +539,8 @@ cf_status slabs_t(cf_plan* pl, int n_slabs, const cx<T>* fin, cx<T>* pout, void*
   CF_HIP(hipStreamWaitEvent(pl->aux, pl->ev_fork, 0), "hipStreamWaitEvent");
   CF_TRY(timed(pl, CF_K_SPECIAL, pl->aux, "special-line launch", [&] {
     return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_special_den, pl->d_special_cp, pl->d_dy,
-                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, pl->aux);
+                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, nullptr, 0,
+                                       pl->d_numflag, pl->aux);
   }));
   CF_HIP(hipEventRecord(pl->ev_join, pl->aux), "hipEventRecord");
   for (int g = 0; g < n_slabs; ++g)
@@ -487,8 +551,10 @@ cf_status slabs_t(cf_plan* pl, int n_slabs, const cx<T>* fin, cx<T>* pout, void*
   return CF_OK;
 }
 
+// psum (nullable): block sums of the pressure a correction solve adds to (see
+// launch_special_lines).
 template <typename T>
-cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
+cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s, const double* psum = nullptr) {
   if constexpr (std::is_same<T, double>::value) {
     if (pl->opt.flags & CF_PLAN_Y_DCT)
       return timed(pl, CF_K_YSOLVE, s, "y-transform solve launch", [&] {
@@ -504,7 +570,8 @@ cf_status solve_t(cf_plan* pl, const cx<T>* fin, cx<T>* pout, hipStream_t s) {
   CF_HIP(hipStreamWaitEvent(pl->aux, pl->ev_fork, 0), "hipStreamWaitEvent");
   CF_TRY(timed(pl, CF_K_SPECIAL, pl->aux, "special-line launch", [&] {
     return cf::launch_special_lines<T>(fin, pout, pl->d_a, pl->d_special_den, pl->d_special_cp, pl->d_dy,
-                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, pl->aux);
+                                       pl->d_special, (int)pl->special.size(), pl->ny, pl->nz, psum,
+                                       psum ? pl->psum_nzb : 0, pl->d_numflag, pl->aux);
   }));
   CF_HIP(hipEventRecord(pl->ev_join, pl->aux), "hipEventRecord");
   CF_TRY(timed(pl, CF_K_YSOLVE, s, "y-solve launch", [&] {
@@ -568,12 +635,15 @@ cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
     CF_TRY(timed(pl, CF_K_R2C_X, s, "residual r2c launch", [&] {
       return cf::launch_r2c_resid<float, float>(rhs.kind, pl->nh, rhs.f, rhs.u, rhs.v, rhs.w, rhs.scale, p, pl->d_a,
                                                 pl->d_c, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx, 1.0 / pl->dz, A,
-                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, s);
+                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, pl->d_psum, s);
     }));
     CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
       return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
     }));
-    CF_TRY(solve_t<float>(pl, B, B, s));
+    // the correction's mean line carries -mean_W(p): the residual is blind to
+    // a constant in p, and the FP32 transforms of the previous solve leave
+    // mean_W(p) off zero by their rounding
+    CF_TRY(solve_t<float>(pl, B, B, s, pl->d_psum));
     CF_TRY(timed(pl, CF_K_FFT_Z_INV, s, "z ifft launch", [&] {
       return cf::launch_fft_z<float>(pl->nz, true, B, A, TB::twz(pl), pl->nkx, pl->ny, s);
     }));
@@ -755,6 +825,7 @@ cf_status tune_partitions(cf_plan* pl, size_t lds_max) {
     for (int LB = 4; LB <= 256; LB *= 2) {
       if (LB * P < 64 || LB * P > 512 || cf::ysolve_lds_needed(pl->ny, P, LB, fp64) > lds_max) continue;
       set_partitions(pl, P, LB);
+      if (upload_blocks(pl) != CF_OK) return done(CF_ERR_DEVICE);
       for (int r = 0; r < kWarm + kRuns && e == hipSuccess; ++r) {
         if (r == kWarm) e = hipEventRecord(e0, s);
         if (e != hipSuccess) break;
@@ -772,7 +843,7 @@ cf_status tune_partitions(cf_plan* pl, size_t lds_max) {
   }
   if (pl->tune.empty()) return done(fail(CF_ERR_UNSUPPORTED, "no partitioning fits"));
   set_partitions(pl, pl->tune[best].P, pl->tune[best].LB);
-  return done(CF_OK);
+  return done(upload_blocks(pl));
 }
 
 }  // namespace
@@ -790,6 +861,7 @@ void cf_options_default(cf_options* opt) {
   opt->refine_passes = 1;
   opt->flags = 0;
   opt->lines_per_block = 0;
+  opt->drop_parts = 0;
 }
 
 const char* cf_status_string(cf_status s) {
@@ -837,6 +909,8 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
                                          : "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16,24,32}");
   if (opt.lines_per_block < 0 || opt.lines_per_block * P > 512)
     return fail(CF_ERR_ARG, "lines_per_block must be >= 0 with lines_per_block * n_parts <= 512");
+  if (opt.drop_parts < 0 || (opt.drop_parts > 0 && (tune || P % opt.drop_parts != 0)))
+    return fail(CF_ERR_ARG, "drop_parts must be 0 or divide n_parts (and be 0 with CF_PLAN_TUNE_PARTS)");
   const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P, ny / P);
   if (opt.precision == CF_MIXED) {
     if (opt.fp64_kx < 1 || opt.fp64_kz < 1) return fail(CF_ERR_ARG, "fp64_kx and fp64_kz must be >= 1");
@@ -1052,6 +1126,16 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
       if ((st = dalloc(pl, &pl->fws, npts)) != CF_OK) return bail(st);
     }
   }
+  if (opt.precision == CF_MIXED && opt.refine_passes > 0) {
+    const int K = cf::r2c_rows<float>(pl->nh);
+    pl->psum_nzb = (nz + K - 1) / K;
+    if ((st = dalloc(pl, &pl->d_psum, (size_t)ny * pl->psum_nzb)) != CF_OK) return bail(st);
+  }
+  if ((st = upload(pl, &pl->d_numflag, std::vector<int>(1, 0))) != CF_OK) return bail(st);
+  // block lists of the partitioned solve (room for one line per block, the
+  // most any lines_per_block can need)
+  if ((st = dalloc(pl, &pl->d_blocks, (size_t)pl->nkx * nz)) != CF_OK) return bail(st);
+  if ((st = upload_blocks(pl)) != CF_OK) return bail(st);
   if ((st = upload(pl, &pl->d_special, pl->special)) != CF_OK) return bail(st);
   {
     std::vector<double> den(pl->special.size() * (size_t)ny), cpv(den.size());
@@ -1087,6 +1171,8 @@ cf_status cf_plan_query(const cf_plan* pl, cf_plan_info* info) {
   info->workspace_bytes = pl->bytes;
   info->lines_per_block = pl->LB;
   info->slab_iface_bytes = (size_t)pl->P * 8 * (size_t)pl->nkx * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
+  info->drop_parts = pl->G;
+  info->n_dropped_lines = pl->n_dropped;
   return CF_OK;
 }
 
@@ -1440,6 +1526,19 @@ cf_status cf_rhs_adjoint(cf_plan* pl, const void* u, const void* v, const void* 
         nullptr, nullptr, 1.0, 0.0, pl->a64, nu, 1.0, 0, static_cast<double*>(gu), static_cast<double*>(gv),
         static_cast<double*>(gw), s);
   });
+}
+
+cf_status cf_plan_numeric_status(cf_plan* pl, void* stream) {
+  CF_TRY(check_plan(pl));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CF_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  CF_HIP(hipStreamSynchronize(pl->aux), "hipStreamSynchronize");
+  int flag = 0;
+  CF_HIP(hipMemcpy(&flag, pl->d_numflag, sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy (numeric flag)");
+  if (!flag) return CF_OK;
+  const int zero = 0;
+  CF_HIP(hipMemcpy(pl->d_numflag, &zero, sizeof(int), hipMemcpyHostToDevice), "hipMemcpy (numeric flag)");
+  return fail(CF_ERR_NUMERIC, "a right-hand side of a pressure solve held a non-finite value");
 }
 
 cf_status cf_plan_set_timing(cf_plan* pl, int enable) {

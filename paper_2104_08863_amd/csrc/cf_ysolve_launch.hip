@@ -35,9 +35,42 @@ int ysolve_default_lb(int P, int M) {
   return lb;
 }
 
+template <typename T, int M, int MODE, bool DROP>
+static hipError_t ysolve_go(long blocks, const int* blist, const YArgs& ya, int threads, int ny, const cx<T>* fin,
+                            cx<T>* pout, const T* a, const T* c, const T* kx2, const T* kz2, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  const size_t lds = MODE == kSlabLocal ? sizeof(T) * 2 * (size_t)ny : ysolve_lds_bytes<T>(ny, ya.P, ya.LB, DROP);
+  hipLaunchKernelGGL((k_ysolve<T, M, MODE, DROP>), dim3(blocks), dim3(threads), lds, s, fin, pout, a, c, kx2, kz2,
+                     blist, ya);
+  return hipGetLastError();
+}
+
+template <typename T, int M>
+static hipError_t ysolve_m(const YLaunch& y, const YArgs& ya, int threads, const cx<T>* fin, cx<T>* pout, const T* a,
+                           const T* c, const T* kx2, const T* kz2, hipStream_t s) {
+  const long all = (y.nlines + ya.LB - 1) / ya.LB;
+  if (y.mode == kSlabLocal) return ysolve_go<T, M, kSlabLocal, false>(all, nullptr, ya, threads, y.ny, fin, pout, a, c,
+                                                                      kx2, kz2, s);
+  // blocks whose lines all allow the drop take the dropped reduced system, the
+  // others the exact one (two launches over the plan's block lists; without
+  // lists every block is exact)
+  const long ne = y.blocks_exact ? y.n_exact : all;
+  hipError_t e;
+  if (y.mode == kSlabFinish) {
+    e = ysolve_go<T, M, kSlabFinish, false>(ne, y.blocks_exact, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+    if (e == hipSuccess && y.blocks_drop)
+      e = ysolve_go<T, M, kSlabFinish, true>(y.n_drop, y.blocks_drop, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+  } else {
+    e = ysolve_go<T, M, kWhole, false>(ne, y.blocks_exact, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+    if (e == hipSuccess && y.blocks_drop)
+      e = ysolve_go<T, M, kWhole, true>(y.n_drop, y.blocks_drop, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+  }
+  return e;
+}
+
 template <typename T>
 hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,
-                         const T* kx2, const T* kz2, T k2drop, hipStream_t s) {
+                         const T* kx2, const T* kz2, hipStream_t s) {
   YArgs ya;
   ya.ny = y.ny;
   ya.nz = y.nz;
@@ -50,8 +83,10 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   ya.pa = y.mode == kWhole ? 0 : y.pa;
   ya.pb = y.mode == kWhole ? y.P : y.pb;
   ya.iface = y.iface;
+  ya.G = y.G > 0 ? y.G : y.P;
   if (y.mode != kWhole && (ya.pa < 0 || ya.pb > y.P || ya.pa >= ya.pb || y.iface == nullptr))
     return hipErrorInvalidValue;
+  if (y.P % ya.G != 0) return hipErrorInvalidValue;
   // A local-mode block holds the threads of its slab's partitions only and no
   // interface data, so it takes more lines (about 256 threads) and only the
   // coefficient rows in LDS.
@@ -59,22 +94,11 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
     const int np = ya.pb - ya.pa;
     while (2 * ya.LB * np <= 256) ya.LB *= 2;
   }
-  const long blocks = (y.nlines + ya.LB - 1) / ya.LB;
-  const size_t lds = y.mode == kSlabLocal ? sizeof(T) * 2 * (size_t)y.ny : ysolve_lds_bytes<T>(y.ny, y.P, ya.LB);
-  const dim3 threads(ya.LB * (y.mode == kSlabLocal ? ya.pb - ya.pa : y.P));
-#define CF_LAUNCH(M, MODE)                                                                        \
-  hipLaunchKernelGGL((k_ysolve<T, M, MODE>), dim3(blocks), threads, lds, s, fin, pout, a, c, kx2, kz2, \
-                     k2drop, ya)
+  const int threads = ya.LB * (y.mode == kSlabLocal ? ya.pb - ya.pa : y.P);
   switch (y.M) {
-#define CF_CASE(M)                 \
-  case M:                          \
-    if (y.mode == kSlabLocal)      \
-      CF_LAUNCH(M, kSlabLocal);    \
-    else if (y.mode == kSlabFinish) \
-      CF_LAUNCH(M, kSlabFinish);   \
-    else                           \
-      CF_LAUNCH(M, kWhole);        \
-    return hipGetLastError();
+#define CF_CASE(M) \
+  case M:          \
+    return ysolve_m<T, M>(y, ya, threads, fin, pout, a, c, kx2, kz2, s);
     CF_FOR_EACH_M(CF_CASE)
 #undef CF_CASE
     default:
@@ -82,15 +106,9 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   }
   if constexpr (std::is_same<T, float>::value) {
     switch (y.M) {
-#define CF_CASE(M)                  \
-  case M:                           \
-    if (y.mode == kSlabLocal)       \
-      CF_LAUNCH(M, kSlabLocal);     \
-    else if (y.mode == kSlabFinish) \
-      CF_LAUNCH(M, kSlabFinish);    \
-    else                            \
-      CF_LAUNCH(M, kWhole);         \
-    return hipGetLastError();
+#define CF_CASE(M) \
+  case M:          \
+    return ysolve_m<T, M>(y, ya, threads, fin, pout, a, c, kx2, kz2, s);
       CF_FOR_EACH_M_FP32(CF_CASE)
 #undef CF_CASE
       default:
@@ -98,33 +116,32 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
     }
   }
   return hipErrorInvalidValue;
-#undef CF_LAUNCH
 }
 
 // Dynamic LDS needed by a y-solve launch (checked by the plan against the
 // device limit).
 size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64) {
-  return fp64 ? ysolve_lds_bytes<double>(ny, P, LB) : ysolve_lds_bytes<float>(ny, P, LB);
+  return fp64 ? ysolve_lds_bytes<double>(ny, P, LB, true) : ysolve_lds_bytes<float>(ny, P, LB, true);
 }
 
 template <typename T>
 hipError_t launch_special_lines(const cx<T>* fin, cx<T>* pout, const double* a, const double* den,
                                 const double* cp, const double* dy, const int* lines, int n_lines,
-                                int ny, int nz, hipStream_t s) {
+                                int ny, int nz, const double* psum, int nzb, int* numflag, hipStream_t s) {
   if (n_lines <= 0) return hipSuccess;
   const int th = 256;
   const size_t lds = sizeof(double) * (5 * (size_t)ny + 3 * th);
   hipLaunchKernelGGL((k_special_lines<T>), dim3(n_lines), dim3(th), lds, s, fin, pout, a, den, cp, dy, lines,
-                     ny, nz);
+                     ny, nz, psum, nzb, numflag);
   return hipGetLastError();
 }
 
 #define CF_INST(T)                                                                                  \
   template hipError_t launch_ysolve<T>(const YLaunch&, const cx<T>*, cx<T>*, const T*, const T*,   \
-                                       const T*, const T*, T, hipStream_t);                        \
+                                       const T*, const T*, hipStream_t);                           \
   template hipError_t launch_special_lines<T>(const cx<T>*, cx<T>*, const double*, const double*, \
                                               const double*, const double*, const int*, int, int, int, \
-                                              hipStream_t);
+                                              const double*, int, int*, hipStream_t);
 CF_INST(double)
 CF_INST(float)
 #undef CF_INST

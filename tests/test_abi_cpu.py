@@ -33,6 +33,12 @@ def test_status_strings_and_defaults():
     lib = L.lib()
     for s in range(6):
         assert lib.cf_status_string(s)
+    assert lib.cf_status_string(L.CF_ERR_NUMERIC) == b"non-finite values"
+    # the status path of the numeric check: a failure reaches the Python caller
+    # as an exception carrying CF_ERR_NUMERIC and the library's message
+    with pytest.raises(L.ChanflowError) as e:
+        L.check(L.CF_ERR_NUMERIC, "cf_plan_numeric_status")
+    assert e.value.status == L.CF_ERR_NUMERIC and "non-finite" in str(e.value)
     opt = L.cf_options()
     lib.cf_options_default(C.byref(opt))
     assert opt.precision == L.CF_FP64 and opt.n_parts == 0 and opt.refine_passes == 1
@@ -136,6 +142,8 @@ def test_calls_reject_null_plan_and_pointers():
     assert lib.cf_plane_stats(None, p, p, p, p, None) == L.CF_ERR_ARG
     assert lib.cf_run_steps(None, p, p, p, p, p, p, 1, 1e-3, 0.01, 0.0, 0, None, None, 0, None) == L.CF_ERR_ARG
     assert lib.cf_plan_query(None, None) == L.CF_ERR_ARG
+    assert lib.cf_solve_spectral_slabs_noalloc(None, 1, p, p, None) == L.CF_ERR_ARG
+    assert lib.cf_plan_numeric_status(None, None) == L.CF_ERR_ARG
     n = C.c_int(-1)
     assert lib.cf_plan_tuning(None, 0, C.byref(n), None, None, None) == L.CF_ERR_ARG
     lib.cf_plan_destroy(None)

@@ -71,36 +71,100 @@ def test_solve_spectral_per_mode(nx, ny, nz, gamma, parts):
     assert np.array_equal(ph2, ph)
 
 
+def _dropped_lines(info, k2, nz):
+    """Lines (kx, kz) the kernel drops: blocks of lines_per_block consecutive
+    lines (line = kx * nz + kz) lying wholly above the plan's threshold."""
+    flat = k2.reshape(-1)                         # (nkx * nz,), line order
+    lb = info["lines_per_block"]
+    ok = np.zeros(flat.size, dtype=bool)
+    for b0 in range(0, flat.size, lb):
+        blk = flat[b0:b0 + lb]
+        ok[b0:b0 + lb] = bool((blk >= info["k2_threshold"]).all())
+    return ok
+
+
 def test_drop_path_matches_oracle_pdd():
-    """A plan with few partitions and a loose tolerance drops the corner terms
+    """A plan with four partitions and a loose tolerance drops the corner terms
     on high-wavenumber lines.  The kernel decides per block of consecutive
-    lines: a block drops only if all its lines may, else it solves exactly.  So
-    every drop-eligible line equals either the oracle's dropped PDD or its
-    exact solve, and some lines must show the dropped result."""
+    lines: a block drops only if all its lines may.  The lines it drops (as
+    many as the plan reports) equal the oracle's dropped PDD, and differ from
+    the exact solve by no more than a small multiple of their corner terms
+    delta; every other line equals the exact solve."""
     nx, ny, nz = 64, 64, 64
     pl, box = plan_for(nx, ny, nz, 2.0, n_parts=4, drop_tol=1e-5)
     info = pl.info()
+    assert info["drop_parts"] == 4
     assert 0 < info["n_drop_lines"] < info["n_lines"]
     rng = np.random.default_rng(4)
     fh = rng.standard_normal((nx // 2 + 1, ny, nz)) + 1j * rng.standard_normal((nx // 2 + 1, ny, nz))
-    ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy().transpose(1, 0, 2)  # (ny, nkx, nz)
-    fh = fh.transpose(1, 0, 2)
+    ph = pl.solve_spectral(torch.tensor(fh, device=dev())).cpu().numpy()      # (nkx, ny, nz)
     a, c, k2 = O.line_coefficients(box)
-    k2 = k2.numpy().T                                                    # (nkx, nz)
-    sel = np.argwhere(k2 >= info["k2_threshold"])
+    k2 = k2.numpy().T.copy()                                                  # (nkx, nz)
+    drop = _dropped_lines(info, k2, nz).reshape(k2.shape)
+    assert drop.sum() == info["n_dropped_lines"] > 0
+    # the singular kx = kz = 0 line (never in a dropping block) takes its gauge
+    mean = O.solve_mean_line(torch.tensor(fh[0, :, 0]), box).numpy()
+    assert np.abs(ph[0, :, 0] - mean).max() <= 1e-11 * np.abs(mean).max()
+    for want_drop in (True, False):
+        sel = np.argwhere(drop == want_drop)
+        sel = sel[(sel[:, 0] > 0) | (sel[:, 1] > 0)]
+        b = -(a + c)[:, None] - torch.tensor(k2[sel[:, 0], sel[:, 1]])[None, :]
+        d = torch.tensor(np.ascontiguousarray(fh[sel[:, 0], :, sel[:, 1]].T))  # (ny, lines)
+        got = ph[sel[:, 0], :, sel[:, 1]].T
+        ref_exact = O.thomas(a[:, None], b, c[:, None], d).numpy()
+        scale = np.abs(ref_exact).max(0)
+        e_exact = np.abs(got - ref_exact).max(0) / scale
+        if want_drop:
+            ref_drop = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
+            assert (np.abs(got - ref_drop).max(0) / scale).max() <= 1e-11
+            delta = O.pdd_indicator(a, b, c, 4).numpy()
+            assert (delta <= 1e-5).all()
+            assert (e_exact <= 50 * delta + 1e-11).all()
+            assert e_exact.max() > 1e-11          # the drop is visible on some lines
+        else:
+            assert e_exact.max() <= 1e-11
+
+
+def test_grouped_drop_on_the_step_grid():
+    """The 1024x256x512 step grid at the default drop tolerance (1e-15): the
+    dropped reduced system is an outer PDD of 4 groups of 4 partitions (64 rows
+    each), whose corner terms fall below 1e-15 for most wavenumbers, so most
+    lines take the dropped 2x2 step.  Every line matches the exact solve
+    (Thomas) to 1e-11, and sampled dropped lines match the oracle's dropped PDD
+    of the same 4 partitions; with drop_tol = 0 nothing is dropped and the
+    result agrees."""
+    wl = synth.WORKLOADS["step550"]
+    pl, box = plan_for(wl.nx, wl.ny, wl.nz, wl.gamma, lx=wl.lx, lz=wl.lz)
+    info = pl.info()
+    assert info["n_parts"] == 16 and info["drop_parts"] == 4
+    assert info["n_dropped_lines"] > 0.9 * info["n_lines"]
+    print(f"step grid: {info['n_drop_lines']} lines above k2 = {info['k2_threshold']:.1f}, "
+          f"{info['n_dropped_lines']} of {info['n_lines']} dropped")
+    rng = np.random.default_rng(8)
+    shape = (pl.nkx, wl.ny, wl.nz)
+    fh = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    fh[0, :, 0].imag = 0.0
+    fg = torch.tensor(fh, device=dev())
+    ph = pl.solve_spectral(fg).cpu().numpy()
+    ref = O.solve_spectral(torch.tensor(fh).permute(1, 2, 0), box).permute(2, 0, 1).numpy()
+    err = np.abs(ph - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    print(f"step grid, dropped reduced system: worst line error vs Thomas {err.max():.3e}")
+    assert err.max() <= 1e-11
+    a, c, k2 = O.line_coefficients(box)
+    k2 = k2.numpy().T.copy()
+    drop = _dropped_lines(info, k2, wl.nz).reshape(k2.shape)
+    assert drop.sum() == info["n_dropped_lines"]
+    sel = np.argwhere(drop)[rng.choice(int(drop.sum()), 256, replace=False)]
     b = -(a + c)[:, None] - torch.tensor(k2[sel[:, 0], sel[:, 1]])[None, :]
-    d = torch.tensor(np.ascontiguousarray(fh[:, sel[:, 0], sel[:, 1]]))
+    d = torch.tensor(np.ascontiguousarray(fh[sel[:, 0], :, sel[:, 1]].T))
     ref_drop = O.pdd_solve(a, b, c, d, 4, drop=True).numpy()
-    ref_exact = O.thomas(a[:, None], b, c[:, None], d).numpy()
-    got = ph[:, sel[:, 0], sel[:, 1]]
-    scale = np.abs(ref_exact).max(0)
-    e_drop = np.abs(got - ref_drop).max(0) / scale
-    e_exact = np.abs(got - ref_exact).max(0) / scale
-    assert np.minimum(e_drop, e_exact).max() <= 1e-11
-    dropped = (e_drop <= 1e-11) & (e_exact > 1e-11)
-    assert dropped.sum() > 0
-    # the drop error stays within the plan's tolerance scale
-    assert e_exact.max() <= 1e-3
+    got = ph[sel[:, 0], :, sel[:, 1]].T
+    assert (np.abs(got - ref_drop).max(0) / np.abs(ref_drop).max(0)).max() <= 1e-11
+    assert (O.pdd_indicator(a, b, c, 4).numpy() <= 1e-15).all()
+    exact, _ = plan_for(wl.nx, wl.ny, wl.nz, wl.gamma, lx=wl.lx, lz=wl.lz, drop_tol=0.0)
+    assert exact.info()["n_dropped_lines"] == 0
+    pe = exact.solve_spectral(fg).cpu().numpy()
+    assert (np.abs(pe - ref).max(axis=1) / np.abs(ref).max(axis=1)).max() <= 1e-11
 
 
 @pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)
@@ -156,3 +220,22 @@ def test_bad_tensor_arguments_rejected():
         pl.poisson_solve(f[:, :, :16])
     with pytest.raises(ValueError):
         pl.poisson_solve(f.transpose(1, 2).contiguous().transpose(1, 2))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_non_finite_right_hand_side_is_reported(precision):
+    """A NaN or an infinity anywhere in f reaches the kx = kz = 0 line of its
+    plane; the solve flags it and cf_plan_numeric_status returns CF_ERR_NUMERIC
+    once (the flag is cleared), while clean solves report nothing."""
+    pl, box = plan_for(32, 16, 24, 2.0, precision=precision)
+    f = torch.tensor(synth.uniform_rhs(32, 16, 24, seed=4), device=dev())
+    pl.poisson_solve(f)
+    assert pl.numeric_status()
+    for j, k, i, bad in [(7, 3, 11, float("nan")), (15, 23, 31, float("inf")), (0, 0, 0, -float("inf"))]:
+        g = f.clone()
+        g[j, k, i] = bad
+        pl.poisson_solve(g)
+        assert not pl.numeric_status(), (j, k, i, bad)
+        assert pl.numeric_status()      # cleared by the read
+    pl.poisson_solve(f)
+    assert pl.numeric_status()

@@ -107,3 +107,29 @@ def test_pdd_fp32_close_to_thomas_at_high_k(H):
     b = -(a + c) - k2
     ref = O.thomas(torch.tensor(a), torch.tensor(b), torch.tensor(c), torch.tensor(d)).numpy()
     assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("ny,Pn,G", [(256, 16, 4), (256, 16, 2), (256, 16, 16), (128, 8, 4), (192, 12, 3),
+                                     (96, 8, 8), (64, 4, 1)])
+def test_grouped_drop_matches_oracle_pdd_of_the_groups(H, ny, Pn, G):
+    """The y kernel's dropped reduced system taken as an outer PDD of G groups
+    of Pn/G partitions (exact inside each group) is the paper's dropped PDD
+    with G partitions: it matches the oracle's pdd_solve(p=G, drop=True) at
+    every k^2, low wavenumbers (where the drop is far from exact) included,
+    and Thomas where the G-level corner terms are below round-off."""
+    a, c = _line_system(ny, 2.5, 0)
+    rng = np.random.default_rng(ny + Pn + G)
+    for k2 in (0.3, 30.0, 3e3, 5e4):
+        d = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+        di = np.ascontiguousarray(np.stack([d.real, d.imag], -1).reshape(-1))
+        x = np.zeros(2 * ny)
+        assert H.cfh_pdd_line_grouped(ny, Pn, G, P(a), P(c), k2, 0, P(di), P(x)) == 0
+        got = x[0::2] + 1j * x[1::2]
+        b = torch.tensor(-(a + c) - k2)[:, None]
+        ref = O.pdd_solve(torch.tensor(a), b, torch.tensor(c), torch.tensor(d)[:, None], G,
+                          drop=True)[:, 0].numpy()
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), k2
+        delta = float(O.pdd_indicator(torch.tensor(a), b, torch.tensor(c), G)[0])
+        th = O.thomas(torch.tensor(a), b[:, 0], torch.tensor(c), torch.tensor(d)).numpy()
+        if delta < 1e-15:
+            assert np.abs(got - th).max() <= 1e-11 * np.abs(th).max(), k2
