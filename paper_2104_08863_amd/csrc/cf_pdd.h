@@ -110,6 +110,33 @@ CF_HD void pdd_local(const T* arow, const T* crow, T k2, cx<T>* d, T* v, T* w) {
   }
 }
 
+// The spike columns v, w of pdd_local alone (the same operations in the same
+// order, so bitwise the same values): the y kernel keeps only their end values
+// through the reduced solve and rebuilds them for step 5, which frees the
+// registers of 2M values while the reduced system is solved.
+template <int M, typename T>
+CF_HD void pdd_spikes(const T* arow, const T* crow, T k2, T* v, T* w) {
+  T cp[M];
+  T rlast = T(0);
+#pragma unroll
+  for (int s = 0; s < M; ++s) {
+    T as = arow[s], cs = crow[s];
+    T bs = -(as + cs) - k2;
+    T cin = (s == M - 1) ? T(0) : cs;
+    T den = (s == 0) ? bs : bs - as * cp[s - 1];
+    T rden = rcp(den);
+    cp[s] = cin * rden;
+    v[s] = (s == 0) ? as * rden : -(as * v[s - 1]) * rden;
+    if (s == M - 1) rlast = rden;
+  }
+  w[M - 1] = crow[M - 1] * rlast;
+#pragma unroll
+  for (int s = M - 2; s >= 0; --s) {
+    v[s] = v[s] - cp[s] * v[s + 1];
+    w[s] = -(cp[s] * w[s + 1]);
+  }
+}
+
 // Step 4 with the corner terms dropped: Cramer's rule on D_i.
 template <typename T>
 CF_HD void pdd_cramer(T wm, T v1n, cx<T> xm, cx<T> x1n, cx<T>& y1, cx<T>& y2) {

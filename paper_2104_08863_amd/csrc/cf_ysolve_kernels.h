@@ -99,11 +99,18 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   const long base = (long)kx * ny * ya.nz + kz + (long)j0 * rs;
 
   cx<T> d[M];
-  T v[M], w[M];
+  T v0 = T(0), vM = T(0), w0 = T(0), wM = T(0);  // end values of the spike columns
 #pragma unroll
   for (int s = 0; s < M; ++s) d[s] = (ok && own) ? fin[base + s * rs] : mk(T(0), T(0));
   __syncthreads();  // coefficients staged
-  if (own) pdd_local<M, T>(sa + j0, sc + j0, k2, d, v, w);
+  if (own) {
+    T v[M], w[M];
+    pdd_local<M, T>(sa + j0, sc + j0, k2, d, v, w);
+    v0 = v[0];
+    vM = v[M - 1];
+    w0 = w[0];
+    wM = w[M - 1];
+  }
 
   T* ifc = static_cast<T*>(ya.iface);
   const long nl = ya.nlines;
@@ -114,10 +121,10 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
       r[1 * nl] = d[0].im;
       r[2 * nl] = d[M - 1].re;
       r[3 * nl] = d[M - 1].im;
-      r[4 * nl] = v[0];
-      r[5 * nl] = v[M - 1];
-      r[6 * nl] = w[0];
-      r[7 * nl] = w[M - 1];
+      r[4 * nl] = v0;
+      r[5 * nl] = vM;
+      r[6 * nl] = w0;
+      r[7 * nl] = wM;
     }
     return;
   }
@@ -125,10 +132,10 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   if (MODE == kWhole) {
     s_x1[me] = d[0];
     s_xm[me] = d[M - 1];
-    s_v1[me] = v[0];
-    s_vm[me] = v[M - 1];
-    s_w1[me] = w[0];
-    s_wm[me] = w[M - 1];
+    s_v1[me] = v0;
+    s_vm[me] = vM;
+    s_w1[me] = w0;
+    s_wm[me] = wM;
   } else {
     // every partition's rows as the local passes wrote them (bitwise equal to
     // this thread's own recomputed values for i in [pa, pb))
@@ -259,7 +266,11 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
     y1p = (i > 0) ? s_y1[(i - 1) * LB + q] : mk(T(0), T(0));
     y2n = (i < Q) ? y2 : mk(T(0), T(0));
   }
-  pdd_correct<M, T>(d, v, w, y1p, y2n);
+  {
+    T v[M], w[M];
+    pdd_spikes<M, T>(sa + j0, sc + j0, k2, v, w);
+    pdd_correct<M, T>(d, v, w, y1p, y2n);
+  }
   if (ok && own && !is_special(kx, kz, ya.nz, ya.skip_kx, ya.skip_kz)) {
 #pragma unroll
     for (int s = 0; s < M; ++s) pout[base + s * rs] = d[s];
