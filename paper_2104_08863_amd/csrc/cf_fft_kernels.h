@@ -126,14 +126,38 @@ k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __r
 // ---------------------------------------------------------------- x (real rows, transposed spectrum)
 template <typename T, int NH>
 struct XCfg {
+  // FP32 blocks keep their twiddle tables (the length-NH table of the passes
+  // and the NH+1 post-processing factors) in LDS: their many small cached loads
+  // inside the barrier-separated passes cost more than the LDS (the FP32 tile
+  // leaves room for them; in FP64 they would halve the blocks per CU).
+  static constexpr bool kLdsTw = sizeof(T) == 4;
+  static constexpr int TWB = kLdsTw ? (2 * NH + 1) * int(sizeof(cx<T>)) : 0;
   // rows per block: aim for 128-byte runs of kz in the transposed spectrum
   static constexpr int KWANT = int(128 / sizeof(cx<T>));
   static constexpr int S = lpad(NH) + 1;  // LDS row stride (holds kx = 0..NH at lpad(kx))
   static constexpr int kfit(int k) {
-    return (k > 1 && (k * S * int(sizeof(cx<T>)) > 147456 || k * FftT<NH>::TPL > 1024)) ? kfit(k / 2) : k;
+    return (k > 1 && (k * S * int(sizeof(cx<T>)) > (kLdsTw ? 159744 - TWB : 147456) || k * FftT<NH>::TPL > 1024))
+               ? kfit(k / 2)
+               : k;
   }
   static constexpr int K = kfit(KWANT);
   static constexpr int THREADS = K * FftT<NH>::TPL;
+};
+
+// The twiddle tables of an x-transform block: copied to LDS when XCfg says so
+// (the caller synchronises before the first use), else the global tables.
+template <typename T, int NH>
+struct XTw {
+  __device__ __forceinline__ static void stage(cx<T>* stw, cx<T>* stwp, const cx<T>*& tw, const cx<T>*& twp) {
+    if constexpr (XCfg<T, NH>::kLdsTw) {
+      for (int q = threadIdx.x; q <= NH; q += XCfg<T, NH>::THREADS) {
+        if (q < NH) stw[q] = tw[q];
+        stwp[q] = twp[q];
+      }
+      tw = stw;
+      twp = stwp;
+    }
+  }
 };
 
 // Row sources for the forward real transform: element pair (x_{2m}, x_{2m+1})
@@ -287,13 +311,16 @@ struct SrcResidual {
 
 template <typename T, int NH, typename Src>
 __global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
-k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* __restrict__ tw, const cx<T>* __restrict__ twp,
-        int ny, int nz) {
+k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz) {
   using F = FftT<NH>;
   constexpr int K = XCfg<T, NH>::K;
   constexpr int S = XCfg<T, NH>::S;
   constexpr int NKX = NH + 1;
+  constexpr int NTW = XCfg<T, NH>::kLdsTw ? NH + 1 : 1;
   __shared__ cx<T> lds[K * S];
+  __shared__ cx<T> stw[NTW], stwp[NTW];
+  XTw<T, NH>::stage(stw, stwp, tw, twp);
+  if constexpr (XCfg<T, NH>::kLdsTw) __syncthreads();
   const int nzb = (nz + K - 1) / K;
   const int j = blockIdx.x / nzb;
   const int k0 = (blockIdx.x % nzb) * K;
@@ -380,13 +407,15 @@ struct DstAccum {
 
 template <typename T, int NH, typename Dst>
 __global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
-k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* __restrict__ tw,
-        const cx<T>* __restrict__ twp, int ny, int nz, T scale) {
+k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* tw, const cx<T>* twp, int ny, int nz, T scale) {
   using F = FftT<NH>;
   constexpr int K = XCfg<T, NH>::K;
   constexpr int S = XCfg<T, NH>::S;
   constexpr int NKX = NH + 1;
+  constexpr int NTW = XCfg<T, NH>::kLdsTw ? NH + 1 : 1;
   __shared__ cx<T> lds[K * S];
+  __shared__ cx<T> stw[NTW], stwp[NTW];
+  XTw<T, NH>::stage(stw, stwp, tw, twp);  // first read after the barrier below
   const int nzb = (nz + K - 1) / K;
   const int j = blockIdx.x / nzb;
   const int k0 = (blockIdx.x % nzb) * K;
