@@ -389,6 +389,28 @@ def profile_fwd_adjoint(steps: int):
         print(f"fwd+adjoint step {k} done", flush=True)
 
 
+def profile_poisson_mixed(calls: int):
+    """Mixed-precision Poisson solves (one refinement pass) on the 2048x512x1536
+    grid, the poisson_mixed_refine1_2048x512x1536 figure's input, one warm-up
+    call, for a kernel-trace or counter profile."""
+    import torch
+
+    from paper_2104_08863_amd import synth
+    from paper_2104_08863_amd.api import Plan
+    dev = torch.device("cuda", 0)
+    big = synth.WORKLOADS["mixed1000"]
+    pm = Plan(big.nx, big.ny, big.nz, big.lx, big.lz, big.y_faces(), precision="mixed", refine_passes=1)
+    vel = synth.powerlaw_velocity_device(big.nx, big.ny, big.nz, seed=0, device=dev)
+    fb = pm.divergence(*vel)
+    del vel
+    torch.cuda.empty_cache()
+    pb = torch.empty_like(fb)
+    for k in range(calls + 1):
+        pm.poisson_solve(fb, out=pb)
+        torch.cuda.synchronize()
+        print(f"mixed Poisson solve {k} done", flush=True)
+
+
 def fwd_adjoint_mixed(steps: int = 2, warmup: int = 1):
     """Mixed-precision forward + adjoint step on the 2048x768x2048 grid (FP32
     state; the gradient overwrites the incoming adjoint field): perturbed
@@ -663,6 +685,9 @@ def main():
     ap.add_argument("--profile-fwd-adjoint-mixed", action="store_true",
                     help="only run two mixed-precision forward + adjoint steps on 2048x768x2048 (for a "
                          "profiler) and exit")
+    ap.add_argument("--profile-poisson-mixed", type=int, default=0, metavar="CALLS",
+                    help="only run CALLS mixed-precision Poisson solves on 2048x512x1536 (after one warm-up "
+                         "call; for a profiler) and exit")
     ap.add_argument("--source-hash", metavar="KERNEL", help="print the source hash a traffic summary of KERNEL "
                     "must carry and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -680,6 +705,9 @@ def main():
         return
     if args.profile_fwd_adjoint_mixed:
         fwd_adjoint_mixed(steps=2, warmup=0)
+        return
+    if args.profile_poisson_mixed:
+        profile_poisson_mixed(args.profile_poisson_mixed)
         return
     if args.profile_fwd_adjoint:
         profile_fwd_adjoint(args.profile_fwd_adjoint)
