@@ -30,14 +30,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 METRIC = "Mpts/s per Poisson solve and per fwd+adjoint step, FP64 vs FP32+refine, % HBM"
 
 # Model bytes per grid point of the metric's legs (every array each pass must
-# read or write once, at its storage precision; the FP64 forward + adjoint step
-# is the sum over the kernels it launches).
+# read or write once, at its storage precision; the forward + adjoint steps are
+# the sum over the kernels they launch).  The mixed solve with one refinement:
+# r2c 8+4, z/y/z^-1 24, the first solve's output stored as FP32 4+4, residual
+# transform 4+8+4, z/y/z^-1 24, accumulation 4+4+8 = 100 (112 if the first
+# solve's output were stored in FP64).
 MODEL_BYTES_PER_POINT = {
     "poisson_fp64": 80,
-    "poisson_mixed_refine1": 112,
+    "poisson_mixed_refine1": 100,
     "step_fp64": 200,
     "fwd_adjoint_step_fp64": 568,
-    "fwd_adjoint_step_mixed": 440,
+    "fwd_adjoint_step_mixed": 416,
 }
 
 # Source files that define each kernel class (the HBM-traffic counters under

@@ -267,7 +267,10 @@ struct SrcDivW {
 // constant in p, so the kernel also sums p (FP64, per block of rows) into
 // psum: the correction solve uses it to restore the gauge mean_W(p) = 0 that
 // the FP32 transforms of the previous solve leave off by their rounding.
-template <typename T, typename In>
+// Tp = float: every row of the FP64 array p holds that row's nx values as
+// FP32 in its first half (the FP32 solve's output before the first correction
+// is added; see DstRows32), read exactly as FP64.
+template <typename T, typename In, typename Tp = double>
 struct SrcResidual {
   static constexpr bool kPSum = true;
   In in;
@@ -277,8 +280,16 @@ struct SrcResidual {
   double rdx2, rdz2;
   int nx, ny, nz;
   double* __restrict__ psum;  // [blocks of k_r2c_x]: the block's sum of p
+  // values 2m, 2m+1 and value i of the row starting at FP64 offset row
+  __device__ __forceinline__ cx<double> pv2(long row, int m) const {
+    const cx<Tp> v = reinterpret_cast<const cx<Tp>*>(reinterpret_cast<const Tp*>(p + row))[m];
+    return mk(double(v.re), double(v.im));
+  }
+  __device__ __forceinline__ double pv1(long row, int i) const {
+    return double(reinterpret_cast<const Tp*>(p + row)[i]);
+  }
   __device__ __forceinline__ double psum_pair(int j, int k, int m) const {
-    const cx<double> pc = reinterpret_cast<const cx<double>*>(p + ((long)j * nz + k) * nx)[m];
+    const cx<double> pc = pv2(((long)j * nz + k) * nx, m);
     return pc.re + pc.im;
   }
   __device__ __forceinline__ cx<T> pair(int j, int k, int m) const {
@@ -289,19 +300,19 @@ struct SrcResidual {
     const int i0 = 2 * m, i1 = 2 * m + 1;
     const int im = (m == 0) ? nx - 1 : i0 - 1, ip = (i1 + 1 == nx) ? 0 : i1 + 1;
     const cx<double> fd = in.pair(j, k, m);
-    const cx<double> pc = reinterpret_cast<const cx<double>*>(p + row)[m];
-    const double pim = p[row + im], pip = p[row + ip];
-    const cx<double> pkp = reinterpret_cast<const cx<double>*>(p + rowp)[m];
-    const cx<double> pkm = reinterpret_cast<const cx<double>*>(p + rowm)[m];
+    const cx<double> pc = pv2(row, m);
+    const double pim = pv1(row, im), pip = pv1(row, ip);
+    const cx<double> pkp = pv2(rowp, m);
+    const cx<double> pkm = pv2(rowm, m);
     double l0 = (pc.im - 2.0 * pc.re + pim) * rdx2 + (pkp.re - 2.0 * pc.re + pkm.re) * rdz2;
     double l1 = (pip - 2.0 * pc.im + pc.re) * rdx2 + (pkp.im - 2.0 * pc.im + pkm.im) * rdz2;
     if (j + 1 < ny) {
-      const cx<double> q = reinterpret_cast<const cx<double>*>(p + row + plane)[m];
+      const cx<double> q = pv2(row + plane, m);
       l0 += c[j] * (q.re - pc.re);
       l1 += c[j] * (q.im - pc.im);
     }
     if (j > 0) {
-      const cx<double> q = reinterpret_cast<const cx<double>*>(p + row - plane)[m];
+      const cx<double> q = pv2(row - plane, m);
       l0 += a[j] * (q.re - pc.re);
       l1 += a[j] * (q.im - pc.im);
     }
@@ -396,6 +407,7 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* tw, const cx<T>* twp, in
 // (j, k), already scaled.
 template <typename T, typename Tout>
 struct DstPlain {
+  static constexpr bool kPre = false;
   Tout* __restrict__ p;
   int nx, nz;
   __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
@@ -404,9 +416,26 @@ struct DstPlain {
   }
 };
 
+// FP32 output packed into FP64 rows: row (j, k) of the FP64 array p receives
+// its nx values as FP32 in the first half of its own bytes.  An FP32 solve
+// that a refinement will correct stores its result this way: the values are
+// exactly those the FP64 store would hold, at half the bytes written here and
+// read by the residual and the accumulation that follow.
+template <typename T>
+struct DstRows32 {
+  static constexpr bool kPre = false;
+  double* __restrict__ p;
+  int nx, nz;
+  __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
+    float* row = reinterpret_cast<float*>(p + ((long)j * nz + k) * nx);
+    reinterpret_cast<cx<float>*>(row)[m] = mk(float(v.re), float(v.im));
+  }
+};
+
 // p += correction (iterative refinement: the correction solve adds to p).
 template <typename T>
 struct DstAccum {
+  static constexpr bool kPre = false;
   double* __restrict__ p;
   int nx, nz;
   __device__ __forceinline__ void put(int j, int k, int m, cx<T> v) const {
@@ -415,6 +444,24 @@ struct DstAccum {
     o.re += double(v.re);
     o.im += double(v.im);
     row[m] = o;
+  }
+};
+
+// p = p32 + correction, p32 packed into the same FP64 rows (DstRows32).  The
+// row's FP32 values are read before the FP64 values are written over them:
+// k_c2r_x loads them (pre) before its first barrier and writes after its
+// last; a block owns its rows, so no other block touches those bytes.
+struct DstAccumRows32 {
+  static constexpr bool kPre = true;
+  double* __restrict__ p;
+  int nx, nz;
+  __device__ __forceinline__ cx<float> pre(int j, int k, int m) const {
+    const float* row = reinterpret_cast<const float*>(p + ((long)j * nz + k) * nx);
+    return reinterpret_cast<const cx<float>*>(row)[m];
+  }
+  __device__ __forceinline__ void put(int j, int k, int m, cx<float> v, cx<float> old) const {
+    cx<double>* row = reinterpret_cast<cx<double>*>(p + ((long)j * nz + k) * nx);
+    row[m] = mk(double(old.re) + double(v.re), double(old.im) + double(v.im));
   }
 };
 
@@ -433,6 +480,20 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* tw, const cx<T>* t
   const int j = blockIdx.x / nzb;
   const int k0 = (blockIdx.x % nzb) * K;
   const long plane = (long)j * NKX;
+  const int tl = threadIdx.x % F::TPL;
+  const int rr = threadIdx.x / F::TPL;
+  const int k = k0 + rr;
+  // the sink's old row values (DstAccumRows32), in the order of the output loop
+  cx<float> pre[Dst::kPre ? F::E : 1];
+  if constexpr (Dst::kPre) {
+#pragma unroll
+    for (int q = 0; q < F::E / F::RL; ++q) {
+      const int b = tl + q * F::TPL;
+#pragma unroll
+      for (int r = 0; r < F::RL; ++r)
+        pre[q * F::RL + r] = (k < nz) ? dst.pre(j, k, b + r * (NH / F::RL)) : mk(0.f, 0.f);
+    }
+  }
   {
     constexpr int TH = XCfg<T, NH>::THREADS;
     constexpr int ITEMS = NKX * K;
@@ -451,10 +512,13 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* tw, const cx<T>* t
       if (idx < ITEMS) lds[(idx % K) * S + lpad(idx / K)] = v[it];
     }
   }
+  if constexpr (Dst::kPre) {
+    // every old value has arrived before the barrier (the block overwrites
+    // these bytes after later barriers)
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) asm volatile("" : : "v"(pre[e].re), "v"(pre[e].im));
+  }
   __syncthreads();
-  const int tl = threadIdx.x % F::TPL;
-  const int rr = threadIdx.x / F::TPL;
-  const int k = k0 + rr;
   cx<T>* sl = lds + rr * S;
   cx<T> x[F::E];
 #pragma unroll
@@ -477,7 +541,12 @@ k_c2r_x(const cx<T>* __restrict__ spec, Dst dst, const cx<T>* tw, const cx<T>* t
     for (int q = 0; q < F::E / F::RL; ++q) {
       const int b = tl + q * F::TPL;
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) dst.put(j, k, b + r * (NH / F::RL), x[q * F::RL + r] * scale);
+      for (int r = 0; r < F::RL; ++r) {
+        if constexpr (Dst::kPre)
+          dst.put(j, k, b + r * (NH / F::RL), x[q * F::RL + r] * scale, pre[q * F::RL + r]);
+        else
+          dst.put(j, k, b + r * (NH / F::RL), x[q * F::RL + r] * scale);
+      }
     }
   }
 }

@@ -103,11 +103,11 @@ int r2c_rows(int nh) {
 template int r2c_rows<double>(int);
 template int r2c_rows<float>(int);
 
-template <typename T, typename In>
-static hipError_t r2c_resid_any(int nh, In in, const double* p, const double* a, const double* c, double rdx,
-                                double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
-                                double* psum, hipStream_t s) {
-  SrcResidual<T, In> src{in, p, a, c, rdx * rdx, rdz * rdz, 2 * nh, ny, nz, psum};
+template <typename T, typename Tp, typename In>
+static hipError_t r2c_resid_n(int nh, In in, const double* p, const double* a, const double* c, double rdx,
+                              double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz,
+                              double* psum, hipStream_t s) {
+  SrcResidual<T, In, Tp> src{in, p, a, c, rdx * rdx, rdz * rdz, 2 * nh, ny, nz, psum};
   switch (nh) {
 #define CF_CASE(N) \
   case N:          \
@@ -119,20 +119,28 @@ static hipError_t r2c_resid_any(int nh, In in, const double* p, const double* a,
   }
 }
 
+template <typename T, typename In>
+static hipError_t r2c_resid_any(int nh, In in, const double* p, bool p32, const double* a, const double* c,
+                                double rdx, double rdz, cx<T>* spec, const cx<T>* tw, const cx<T>* twp, int ny,
+                                int nz, double* psum, hipStream_t s) {
+  if (p32) return r2c_resid_n<T, float>(nh, in, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, psum, s);
+  return r2c_resid_n<T, double>(nh, in, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, psum, s);
+}
+
 template <typename T, typename Ts>
 hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
-                            double scale, const double* p, const double* a, const double* c, const double* rdy,
-                            const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
-                            const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s) {
+                            double scale, const double* p, bool p32, const double* a, const double* c,
+                            const double* rdy, const double* rdyc, double rdx, double rdz, cx<T>* spec,
+                            const cx<T>* tw, const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s) {
   const int nx = 2 * nh;
   if (kind == 0)
-    return r2c_resid_any<T>(nh, SrcPlain<double, double>{f, nx, nz}, p, a, c, rdx, rdz, spec, tw, twp, ny, nz, psum,
-                            s);
+    return r2c_resid_any<T>(nh, SrcPlain<double, double>{f, nx, nz}, p, p32, a, c, rdx, rdz, spec, tw, twp, ny, nz,
+                            psum, s);
   if (kind == 1)
-    return r2c_resid_any<T>(nh, SrcDiv<double, Ts>{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz}, p, a, c, rdx, rdz,
-                            spec, tw, twp, ny, nz, psum, s);
-  return r2c_resid_any<T>(nh, SrcDivW<double, Ts>{u, v, w, rdy, rdyc, rdx, rdz, nx, ny, nz}, p, a, c, rdx, rdz,
-                          spec, tw, twp, ny, nz, psum, s);
+    return r2c_resid_any<T>(nh, SrcDiv<double, Ts>{u, v, w, rdy, rdx, rdz, scale, nx, ny, nz}, p, p32, a, c, rdx,
+                            rdz, spec, tw, twp, ny, nz, psum, s);
+  return r2c_resid_any<T>(nh, SrcDivW<double, Ts>{u, v, w, rdy, rdyc, rdx, rdz, nx, ny, nz}, p, p32, a, c, rdx,
+                          rdz, spec, tw, twp, ny, nz, psum, s);
 }
 
 template <typename T, typename Ts>
@@ -198,7 +206,22 @@ template hipError_t launch_r2c_divw<double, double>(int, const double*, const do
 
 template <typename T>
 hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
-                            int nz, T scale, hipStream_t s) {
+                            int nz, T scale, bool p32, hipStream_t s) {
+  if (p32) {
+    if constexpr (std::is_same<T, float>::value) {
+      DstAccumRows32 dst{p, 2 * nh, nz};
+      switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return c2r_n<T, N>(spec, dst, tw, twp, ny, nz, scale, s);
+        CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+        default:
+          return hipErrorInvalidValue;
+      }
+    }
+    return hipErrorInvalidValue;
+  }
   DstAccum<T> dst{p, 2 * nh, nz};
   switch (nh) {
 #define CF_CASE(N) \
@@ -211,8 +234,23 @@ hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* t
   }
 }
 
+template <typename T>
+hipError_t launch_c2r_rows32(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
+                             int nz, T scale, hipStream_t s) {
+  DstRows32<T> dst{p, 2 * nh, nz};
+  switch (nh) {
+#define CF_CASE(N) \
+  case N:          \
+    return c2r_n<T, N>(spec, dst, tw, twp, ny, nz, scale, s);
+    CF_FOR_EACH_LEN(CF_CASE)
+#undef CF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 template hipError_t launch_r2c_resid<float, float>(int, int, const double*, const float*, const float*,
-                                                   const float*, double, const double*, const double*,
+                                                   const float*, double, const double*, bool, const double*,
                                                    const double*, const double*, const double*, double, double,
                                                    cx<float>*, const cx<float>*, const cx<float>*, int, int,
                                                    double*, hipStream_t);
@@ -223,7 +261,9 @@ template hipError_t launch_r2c_div_t<float, float>(int, const float*, const floa
                                                    const double*, double, double, double, cx<float>*,
                                                    const cx<float>*, const cx<float>*, int, int, hipStream_t);
 template hipError_t launch_c2r_accum<float>(int, const cx<float>*, double*, const cx<float>*,
-                                            const cx<float>*, int, int, float, hipStream_t);
+                                            const cx<float>*, int, int, float, bool, hipStream_t);
+template hipError_t launch_c2r_rows32<float>(int, const cx<float>*, double*, const cx<float>*,
+                                             const cx<float>*, int, int, float, hipStream_t);
 
 #define CF_INST(T)                                                                                   \
   template hipError_t launch_fft_z<T>(int, bool, const cx<T>*, cx<T>*, const cx<T>*, int, int, hipStream_t); \

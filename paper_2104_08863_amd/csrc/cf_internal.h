@@ -32,12 +32,13 @@ hipError_t launch_r2c_div(int nh, const double* u, const double* v, const double
 // (kind 0), scale * D(u, v, w) (kind 1) or D(u / W, v / W, w / W) (kind 2).
 // psum: one double per block, the block's FP64 sum of p; block (j, b) covers
 // rows k = b*K .. b*K+K-1 of plane j and is entry j * ceil(nz/K) + b, with K =
-// r2c_rows<T>(nh).
+// r2c_rows<T>(nh).  p32: p holds FP32 rows packed into its FP64 rows (as
+// launch_c2r_rows32 writes them).
 template <typename T, typename Ts>
 hipError_t launch_r2c_resid(int kind, int nh, const double* f, const Ts* u, const Ts* v, const Ts* w,
-                            double scale, const double* p, const double* a, const double* c, const double* rdy,
-                            const double* rdyc, double rdx, double rdz, cx<T>* spec, const cx<T>* tw,
-                            const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s);
+                            double scale, const double* p, bool p32, const double* a, const double* c,
+                            const double* rdy, const double* rdyc, double rdx, double rdz, cx<T>* spec,
+                            const cx<T>* tw, const cx<T>* twp, int ny, int nz, double* psum, hipStream_t s);
 // Rows per block of the x transforms of half-length nh.
 template <typename T>
 int r2c_rows(int nh);
@@ -68,10 +69,17 @@ template <typename T>
 hipError_t launch_correct_w(const T* gu, const T* gv, const T* gw, T* ou, T* ov, T* ow, const double* phi,
                             const AdjGeo<T>& g, hipStream_t st);
 
-// Inverse real transform added into p (refinement correction).
+// Inverse real transform added into p (refinement correction).  p32 (FP32
+// only): p holds FP32 rows packed into its FP64 rows; the result is FP64.
 template <typename T>
 hipError_t launch_c2r_accum(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
-                            int nz, T scale, hipStream_t s);
+                            int nz, T scale, bool p32, hipStream_t s);
+
+// Inverse real transform stored as FP32 into the first half of each FP64 row
+// of p (a solve whose result a refinement pass corrects next).
+template <typename T>
+hipError_t launch_c2r_rows32(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp, int ny,
+                             int nz, T scale, hipStream_t s);
 
 template <typename T>
 hipError_t launch_c2r_plain(int nh, const cx<T>* spec, double* p, const cx<T>* tw, const cx<T>* twp,

@@ -602,7 +602,11 @@ struct MixedRhs {
 
 // Mixed-precision Poisson solve: p0 = S32(f), then refine_passes times
 // p += S32(f - L_h p) with the residual formed in FP64.  S32 runs the transforms
-// and the bulk PDD in FP32 and the FP64 line set in FP64.
+// and the bulk PDD in FP32 and the FP64 line set in FP64.  p0 comes out of an
+// FP32 transform, so when a refinement follows it is stored as FP32, packed
+// into the first half of each FP64 row of p (the same values at half the
+// bytes); the residual reads it from there and the first correction writes
+// the FP64 sum over it.
 cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
   using TB = Tabs<float>;
   cx<float>* A = static_cast<cx<float>*>(pl->specA);
@@ -629,13 +633,24 @@ cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
     }));
   }
   CF_TRY(solve_t<float>(pl, B, B, s));
-  CF_TRY(inverse_t<float>(pl, B, p, s));
   const float scl = float(1.0 / ((double)pl->nx * (double)pl->nz));
+  const bool p32 = pl->opt.refine_passes > 0;
+  if (p32) {
+    CF_TRY(timed(pl, CF_K_FFT_Z_INV, s, "z ifft launch", [&] {
+      return cf::launch_fft_z<float>(pl->nz, true, B, A, TB::twz(pl), pl->nkx, pl->ny, s);
+    }));
+    CF_TRY(timed(pl, CF_K_C2R_X, s, "c2r launch", [&] {
+      return cf::launch_c2r_rows32<float>(pl->nh, A, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scl, s);
+    }));
+  } else {
+    CF_TRY(inverse_t<float>(pl, B, p, s));
+  }
   for (int it = 0; it < pl->opt.refine_passes; ++it) {
+    const bool in32 = p32 && it == 0;  // p still holds the packed FP32 rows
     CF_TRY(timed(pl, CF_K_R2C_X, s, "residual r2c launch", [&] {
-      return cf::launch_r2c_resid<float, float>(rhs.kind, pl->nh, rhs.f, rhs.u, rhs.v, rhs.w, rhs.scale, p, pl->d_a,
-                                                pl->d_c, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx, 1.0 / pl->dz, A,
-                                                TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, pl->d_psum, s);
+      return cf::launch_r2c_resid<float, float>(rhs.kind, pl->nh, rhs.f, rhs.u, rhs.v, rhs.w, rhs.scale, p, in32,
+                                                pl->d_a, pl->d_c, pl->d_rdy, pl->d_rdyc, 1.0 / pl->dx, 1.0 / pl->dz,
+                                                A, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, pl->d_psum, s);
     }));
     CF_TRY(timed(pl, CF_K_FFT_Z_FWD, s, "z fft launch", [&] {
       return cf::launch_fft_z<float>(pl->nz, false, A, B, TB::twz(pl), pl->ny, pl->nkx, s);
@@ -648,7 +663,7 @@ cf_status poisson_mixed(cf_plan* pl, MixedRhs rhs, double* p, hipStream_t s) {
       return cf::launch_fft_z<float>(pl->nz, true, B, A, TB::twz(pl), pl->nkx, pl->ny, s);
     }));
     CF_TRY(timed(pl, CF_K_C2R_X, s, "c2r accumulate launch", [&] {
-      return cf::launch_c2r_accum<float>(pl->nh, A, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scl, s);
+      return cf::launch_c2r_accum<float>(pl->nh, A, p, TB::twx(pl), TB::twp(pl), pl->ny, pl->nz, scl, in32, s);
     }));
   }
   return CF_OK;
