@@ -57,8 +57,10 @@ enum { CF_FP64 = 0, CF_MIXED = 1 };
 typedef struct {
   int precision;      /* CF_FP64 (all arithmetic FP64) or CF_MIXED (FP32 transforms and
                          bulk wall-normal solves, FP64 low-wavenumber lines and residual) */
-  int n_parts;        /* PDD partitions per wall-normal line; 0 = automatic. ny/n_parts
-                         must be one of 1,2,3,4,6,8,12,16 (CF_MIXED: also 24, 32) */
+  int n_parts;        /* PDD partitions P per wall-normal line; 0 = automatic.  Each
+                         partition has M = ceil(ny/P) rows, M one of 1,2,3,4,6,8,12,16
+                         (CF_MIXED: also 24, 32), with (P-1)*M < ny; when P does not
+                         divide ny the last partition is padded with decoupled rows */
   double drop_tol;    /* lines whose PDD corner terms are all <= drop_tol use the dropped
                          (2x2) reduced system; the others the exact one.  < 0 = default
                          (1e-15 FP64, 1e-7 mixed) */
@@ -83,8 +85,8 @@ typedef struct {
    relative), CF_FP64, and an even ny of the form 2^a or 3*2^a, at most 2048. */
 /* CF_PLAN_TUNE_PARTS: choose the partitioning by measurement (Section 2.2 leaves
    the count P and the placement to the solver): at creation the plan times the
-   partitioned solve for every admissible P (ny = P*M, M in {1,2,3,4,6,8,12,16},
-   in CF_MIXED also 24 and 32, P <= 64) and every block of lines_per_block = 4, 8, ..., 256 lines with
+   partitioned solve for every admissible P (M = ceil(ny/P) in {1,2,3,4,6,8,12,16},
+   in CF_MIXED also 24 and 32, (P-1)*M < ny, P <= 64) and every block of lines_per_block = 4, 8, ..., 256 lines with
    64 <= lines_per_block * P <= 512 that fits in LDS (five launches each, after
    two warm-up launches, in place on zeros in the plan's workspace), keeps the
    fastest and sets the drop threshold for its P (each candidate's accuracy
@@ -97,7 +99,7 @@ enum { CF_PLAN_STEP = 1, CF_PLAN_ADJOINT = 2, CF_PLAN_Y_DCT = 4, CF_PLAN_TUNE_PA
 typedef struct {
   int nx, ny, nz, precision;
   int n_parts;            /* partitions per line (P) */
-  int rows_per_part;      /* ny / P */
+  int rows_per_part;      /* M = ceil(ny / P) */
   long long n_lines;      /* (nx/2+1) * nz */
   long long n_drop_lines; /* lines whose corner terms fall below drop_tol */
   long long n_special;    /* lines solved by whole-line FP64 Thomas */
@@ -119,8 +121,12 @@ void cf_options_default(cf_options* opt);
  * Create a plan on the current HIP device (Section 2 problem setup: Eq. (8)-(9)
  * operator, modified wavenumbers, PDD partitioning of Section 2.2).
  * nx, nz: even, 2^a or 3*2^a, nx/2 and nz in [2, 2048] (nz >= 2).
- * ny >= 2 and ny = P*M with M in {1,2,3,4,6,8,12,16} (CF_MIXED: also 24, 32) and
- * P <= 64; the automatic P is the fewest such partitions, preferring powers of two.
+ * ny >= 2, split into P <= 64 partitions of M = ceil(ny/P) rows with M in
+ * {1,2,3,4,6,8,12,16} (CF_MIXED: also 24, 32) and (P-1)*M < ny: any ny up to
+ * 1024 (CF_MIXED: 2048).  The automatic P is the fewest partitions that divide
+ * ny, preferring powers of two, else the partitioning with the fewest padding
+ * rows (the rows P*M - ny that complete the last partition: no-flux rows below
+ * the top wall row, decoupled from the line).
  * y_faces: host, ny+1 strictly increasing finite values (walls at both ends).
  * opt: NULL for defaults.  On success *out receives the plan; on failure *out is
  * set to NULL and nothing is leaked.

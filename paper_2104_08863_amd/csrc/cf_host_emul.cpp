@@ -4,6 +4,7 @@
 // code as the device kernels (all taken from the shared headers), visiting the
 // threads of a line one after another, so the arithmetic of the kernels can be
 // checked on a machine without a GPU.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -199,13 +200,19 @@ void pdd_line_grouped_m(int P, int G, const T* a, const T* c, T k2, std::vector<
   }
 }
 
+// Both line emulations split the ny rows into P partitions of M = ceil(ny/P)
+// rows like the plan: the rows past ny complete the last partition with
+// a = c = 0 and a zero right-hand side.
 template <typename T>
 int pdd_line_grouped(int ny, int P, int G, const double* a, const double* c, double k2, const double* din,
                      double* xout) {
-  if (P < 1 || ny % P || G < 1 || P % G) return 1;
-  const int M = ny / P;
-  std::vector<T> at(a, a + ny), ct(c, c + ny);
-  std::vector<cx<T>> d(ny);
+  if (P < 1 || G < 1 || P % G) return 1;
+  const int M = (ny + P - 1) / P;
+  if ((P - 1) * M >= ny) return 1;
+  std::vector<T> at(P * M, T(0)), ct(P * M, T(0));
+  std::copy(a, a + ny, at.begin());
+  std::copy(c, c + ny, ct.begin());
+  std::vector<cx<T>> d(P * M, mk(T(0), T(0)));
   for (int j = 0; j < ny; ++j) d[j] = mk((T)din[2 * j], (T)din[2 * j + 1]);
   switch (M) {
 #define CF_CASE(MM)                                                         \
@@ -227,10 +234,13 @@ int pdd_line_grouped(int ny, int P, int G, const double* a, const double* c, dou
 template <typename T>
 int pdd_line(int ny, int P, const double* a, const double* c, double k2, int exact, const double* din,
              double* xout) {
-  if (P < 1 || ny % P) return 1;
-  const int M = ny / P;
-  std::vector<T> at(a, a + ny), ct(c, c + ny);
-  std::vector<cx<T>> d(ny);
+  if (P < 1) return 1;
+  const int M = (ny + P - 1) / P;
+  if ((P - 1) * M >= ny) return 1;
+  std::vector<T> at(P * M, T(0)), ct(P * M, T(0));
+  std::copy(a, a + ny, at.begin());
+  std::copy(c, c + ny, ct.begin());
+  std::vector<cx<T>> d(P * M, mk(T(0), T(0)));
   for (int j = 0; j < ny; ++j) d[j] = mk((T)din[2 * j], (T)din[2 * j + 1]);
   switch (M) {
 #define CF_CASE(MM)                                                     \

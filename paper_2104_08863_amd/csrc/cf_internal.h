@@ -105,7 +105,7 @@ struct YLaunch {
 // Default lines per block of the partitioned solve for P partitions.
 int ysolve_default_lb(int P, int M);
 // Dynamic LDS of one partitioned-solve block.
-size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64);
+size_t ysolve_lds_needed(int nyp, int P, int LB, bool fp64);
 
 template <typename T>
 hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const T* a, const T* c,

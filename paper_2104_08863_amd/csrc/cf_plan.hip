@@ -290,7 +290,7 @@ cf_status harvest(cf_plan* pl) {
 // a_first e_1 and A_g w = c_last e_last (Thomas, FP64), and the corner terms are
 // v at its last row and w at its first.
 double corner_delta(const cf_plan* pl, double k2) {
-  const int G = pl->G, Mg = pl->ny / G;
+  const int G = pl->G, Mg = pl->P * pl->M / G;  // interior groups hold no padding rows
   double delta = 0.0;
   std::vector<double> cp(Mg), v(Mg), w(Mg);
   for (int g = 1; g + 1 < G; ++g) {
@@ -320,13 +320,24 @@ double corner_delta(const cf_plan* pl, double k2) {
 // enough on the stretched workload grids for most wavenumbers), else P.
 int auto_drop_parts(int P) { return (P % 4 == 0) ? 4 : P; }
 
-// Partitioning of the wall-normal lines into P parts of M = ny/P rows (Section
-// 2.2), the outer partitions G of the dropped reduced system, and the drop
-// threshold that goes with them: the smallest k^2 whose G-level corner terms
-// are all <= drop_tol (the corner terms fall monotonically with k^2).
+// Zero rows after the wall-normal coefficient tables: more than any
+// partitioning pads (fewer than the largest compiled row count, 32).
+constexpr int kPadRows = 32;
+
+// Rows per partition when ny is split into P parts: M = ceil(ny/P); when P
+// does not divide ny the last partition is completed by P*M - ny < M padding
+// rows (a = c = 0 in the line solve's tables, zero right-hand side; below the
+// wall row, whose c is 0, they are decoupled from the line).
+int part_rows(int ny, int P) { return (ny + P - 1) / P; }
+
+// Partitioning of the wall-normal lines into P parts of M = part_rows(ny, P)
+// rows (Section 2.2), the outer partitions G of the dropped reduced system,
+// and the drop threshold that goes with them: the smallest k^2 whose G-level
+// corner terms are all <= drop_tol (the corner terms fall monotonically with
+// k^2).
 void set_partitions(cf_plan* pl, int P, int LB) {
   pl->P = P;
-  pl->M = pl->ny / P;
+  pl->M = part_rows(pl->ny, P);
   pl->LB = LB;
   pl->G = (pl->opt.drop_parts > 0 && P % pl->opt.drop_parts == 0) ? pl->opt.drop_parts : auto_drop_parts(P);
   double kmax = 0.0;
@@ -380,18 +391,26 @@ cf_status upload_blocks(cf_plan* pl) {
   return CF_OK;
 }
 
-int auto_parts(int ny, bool fp64) {
-  // fewest partitions with a compiled row count (at most 16 rows in FP64, 32 in
-  // FP32), preferring powers of two
-  for (int P = 1; P <= 64; P *= 2)
-    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64)) return P;
-  for (int P = 1; P <= 64; ++P)
-    if (ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64)) return P;
-  return 0;
+// P parts of part_rows(ny, P) rows with a compiled row count, P <= 64, every
+// part holding at least one row of the line.
+bool parts_ok(int ny, int P, bool fp64) {
+  if (P < 1 || P > 64) return false;
+  const int M = part_rows(ny, P);
+  return cf::ysolve_m_compiled(M, fp64) && (P - 1) * M < ny;
 }
 
-bool parts_ok(int ny, int P, bool fp64) {
-  return P >= 1 && P <= 64 && ny % P == 0 && cf::ysolve_m_compiled(ny / P, fp64);
+int auto_parts(int ny, bool fp64) {
+  // fewest partitions with a compiled row count (at most 16 rows in FP64, 32 in
+  // FP32) that divide ny, preferring powers of two; if none divides ny, the
+  // partitioning with the fewest padding rows (then the fewest partitions)
+  for (int P = 1; P <= 64; P *= 2)
+    if (ny % P == 0 && parts_ok(ny, P, fp64)) return P;
+  for (int P = 1; P <= 64; ++P)
+    if (ny % P == 0 && parts_ok(ny, P, fp64)) return P;
+  int best = 0;
+  for (int P = 1; P <= 64; ++P)
+    if (parts_ok(ny, P, fp64) && (best == 0 || P * part_rows(ny, P) < best * part_rows(ny, best))) best = P;
+  return best;
 }
 
 cf_status check_plan(const cf_plan* pl) {
@@ -812,7 +831,8 @@ void special_factors(const cf_plan* pl, int line, double* den, double* cp) {
 
 // Partition count and block shape by measurement (the count and placement
 // question of Section 2.2, answered on the device): every P with ny = P*M for
-// a compiled M, P <= 64, and every block of LB lines with 64 <= LB*P <= 512
+// a compiled M, P <= 64 (if there is none, every padded partitioning that
+// parts_ok admits), and every block of LB lines with 64 <= LB*P <= 512
 // threads that fits in LDS, is timed over five launches of the partitioned
 // solve (in place, on zeros in the plan's spectral workspace, on the plan's
 // capture stream, after two warm-up launches); the fastest is kept and the drop
@@ -835,10 +855,14 @@ cf_status tune_partitions(cf_plan* pl, size_t lds_max) {
   constexpr int kWarm = 2, kRuns = 5;
   pl->tune.clear();
   size_t best = 0;
+  // the partition counts that divide ny, or the padded ones when none does
+  bool any_exact = false;
+  for (int P = 1; P <= 64; ++P) any_exact = any_exact || (pl->ny % P == 0 && parts_ok(pl->ny, P, fp64));
   for (int P = 1; P <= 64; ++P) {
-    if (!parts_ok(pl->ny, P, fp64)) continue;
+    if (!parts_ok(pl->ny, P, fp64) || (any_exact && pl->ny % P != 0)) continue;
     for (int LB = 4; LB <= 256; LB *= 2) {
-      if (LB * P < 64 || LB * P > 512 || cf::ysolve_lds_needed(pl->ny, P, LB, fp64) > lds_max) continue;
+      if (LB * P < 64 || LB * P > 512 || cf::ysolve_lds_needed(P * part_rows(pl->ny, P), P, LB, fp64) > lds_max)
+        continue;
       set_partitions(pl, P, LB);
       if (upload_blocks(pl) != CF_OK) return done(CF_ERR_DEVICE);
       for (int r = 0; r < kWarm + kRuns && e == hipSuccess; ++r) {
@@ -920,13 +944,16 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   const bool fp64 = opt.precision == CF_FP64;
   if (P == 0) P = auto_parts(ny, fp64);
   if (P == 0 || !parts_ok(ny, P, fp64))
-    return fail(CF_ERR_UNSUPPORTED, fp64 ? "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16}"
-                                         : "ny must be P*M with P <= 64 and M in {1,2,3,4,6,8,12,16,24,32}");
+    return fail(CF_ERR_UNSUPPORTED,
+                fp64 ? "ny needs P <= 64 partitions of M = ceil(ny/P) rows, M in {1,2,3,4,6,8,12,16}, "
+                       "(P-1)*M < ny"
+                     : "ny needs P <= 64 partitions of M = ceil(ny/P) rows, M in {1,2,3,4,6,8,12,16,24,32}, "
+                       "(P-1)*M < ny");
   if (opt.lines_per_block < 0 || opt.lines_per_block * P > 512)
     return fail(CF_ERR_ARG, "lines_per_block must be >= 0 with lines_per_block * n_parts <= 512");
   if (opt.drop_parts < 0 || (opt.drop_parts > 0 && (tune || P % opt.drop_parts != 0)))
     return fail(CF_ERR_ARG, "drop_parts must be 0 or divide n_parts (and be 0 with CF_PLAN_TUNE_PARTS)");
-  const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P, ny / P);
+  const int LB = opt.lines_per_block > 0 ? opt.lines_per_block : cf::ysolve_default_lb(P, part_rows(ny, P));
   if (opt.precision == CF_MIXED) {
     if (opt.fp64_kx < 1 || opt.fp64_kz < 1) return fail(CF_ERR_ARG, "fp64_kx and fp64_kz must be >= 1");
     if (opt.refine_passes < 0 || opt.refine_passes > 8) return fail(CF_ERR_ARG, "refine_passes must be in [0, 8]");
@@ -954,7 +981,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   pl->dz = lz / nz;
   pl->opt = opt;
   pl->P = P;
-  pl->M = ny / P;
+  pl->M = part_rows(ny, P);
   pl->yf.assign(y_faces, y_faces + ny + 1);
   pl->dy.resize(ny);
   for (int j = 0; j < ny; ++j) pl->dy[j] = pl->yf[j + 1] - pl->yf[j];
@@ -962,9 +989,10 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
   for (int j = 0; j < ny; ++j) yc[j] = 0.5 * (pl->yf[j] + pl->yf[j + 1]);
   pl->dyc.resize(ny - 1);
   for (int j = 0; j + 1 < ny; ++j) pl->dyc[j] = yc[j + 1] - yc[j];
-  // wall-normal rows of L_h = D o G (no flux through the walls)
-  pl->a.assign(ny, 0.0);
-  pl->c.assign(ny, 0.0);
+  // wall-normal rows of L_h = D o G (no flux through the walls), followed by
+  // zeros for the padding rows of any partitioning (fewer than 32)
+  pl->a.assign(ny + kPadRows, 0.0);
+  pl->c.assign(ny + kPadRows, 0.0);
   for (int j = 1; j < ny; ++j) pl->a[j] = 1.0 / (pl->dy[j] * pl->dyc[j - 1]);
   for (int j = 0; j + 1 < ny; ++j) pl->c[j] = 1.0 / (pl->dy[j] * pl->dyc[j]);
   // modified wavenumbers: -(2 sin(pi k/n)/d)^2 are the eigenvalues of the periodic second difference
@@ -1009,7 +1037,7 @@ cf_status cf_plan_create(cf_plan** out, int nx, int ny, int nz, double lx, doubl
     delete pl;
     return dev_fail(e, "hipGetSymbolAddress (interface-row scratch)");
   }
-  const size_t lds_need = cf::ysolve_lds_needed(ny, P, LB, opt.precision == CF_FP64);
+  const size_t lds_need = cf::ysolve_lds_needed(P * pl->M, P, LB, opt.precision == CF_FP64);
   if (lds_need > (size_t)lds_max) {
     delete pl;
     return fail(CF_ERR_UNSUPPORTED, "partitioning needs " + std::to_string(lds_need) + " bytes of LDS per block");

@@ -44,7 +44,8 @@ __device__ __forceinline__ bool is_special(int kx, int kz, int nz, int skip_kx, 
   return (kx == 0 && kz == 0) || (kx < skip_kx && kzs < skip_kz);
 }
 
-// Dynamic LDS layout: a[ny], c[ny] (T), then per (partition, line):
+// Dynamic LDS layout: a[nyp], c[nyp] (T; nyp = P*M rows, see k_ysolve), then
+// per (partition, line):
 //   interface data: x1, xm (cx), v1, vm, w1, wm (T)  -> arrays [P][LB]
 //   results y1, y2 (cx) [P][LB]
 //   reduced rows zrow<T> [P][LB] (16 planes), or in the dropped form zrow3<T>
@@ -52,8 +53,8 @@ __device__ __forceinline__ bool is_special(int kx, int kz, int nz, int skip_kx, 
 //   outer partition g and line, the group's end values xg_m, xg_1 (cx), wg_m,
 //   vg_1 (T) and the outer interface results Y1, Y2 (cx)
 template <typename T>
-__host__ __device__ constexpr size_t ysolve_lds_bytes(int ny, int P, int LB, bool drop) {
-  return sizeof(T) * 2 * ny +
+__host__ __device__ constexpr size_t ysolve_lds_bytes(int nyp, int P, int LB, bool drop) {
+  return sizeof(T) * 2 * nyp +
          (sizeof(cx<T>) * 4 + sizeof(T) * 4 + (drop ? sizeof(zrow3<T>) : sizeof(zrow<T>))) * size_t(P) * LB;
 }
 
@@ -61,16 +62,21 @@ __host__ __device__ constexpr size_t ysolve_lds_bytes(int ny, int P, int LB, boo
 // launch covers only such blocks) and the reduced system takes the dropped
 // form; otherwise it is solved exactly.  blist (nullable): the blocks of the
 // launch, as indices of LB-line blocks (identity when null).
+// The P partitions of M rows cover nyp = P*M >= ny rows: rows j >= ny (fewer
+// than M, all in the last partition) are padding with a = c = 0 in the
+// coefficient tables and a zero right-hand side.  The wall row ny-1 has c = 0,
+// so they are decoupled from the line (each solves -k^2 x = 0); they are never
+// loaded or stored.
 template <typename T, int M, int MODE, bool DROP>
 __global__ void __launch_bounds__(512)
 k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
          const T* __restrict__ ccoef, const T* __restrict__ kx2, const T* __restrict__ kz2,
          const int* __restrict__ blist, YArgs ya) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int LB = ya.LB, P = ya.P, ny = ya.ny;
+  const int LB = ya.LB, P = ya.P, ny = ya.ny, nyp = P * M;
   T* sa = reinterpret_cast<T*>(smem);
-  T* sc = sa + ny;
-  cx<T>* s_x1 = reinterpret_cast<cx<T>*>(sc + ny);
+  T* sc = sa + nyp;
+  cx<T>* s_x1 = reinterpret_cast<cx<T>*>(sc + nyp);
   cx<T>* s_xm = s_x1 + P * LB;
   cx<T>* s_y1 = s_xm + P * LB;
   cx<T>* s_y2 = s_y1 + P * LB;
@@ -80,7 +86,7 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   T* s_wm = s_w1 + P * LB;
   T* s_red = s_wm + P * LB;  // reduced rows: 16 planes (exact) or 20 (dropped) of P * LB values
 
-  for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+  for (int j = threadIdx.x; j < nyp; j += blockDim.x) {
     sa[j] = acoef[j];
     sc[j] = ccoef[j];
   }
@@ -101,7 +107,7 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   cx<T> d[M];
   T v0 = T(0), vM = T(0), w0 = T(0), wM = T(0);  // end values of the spike columns
 #pragma unroll
-  for (int s = 0; s < M; ++s) d[s] = (ok && own) ? fin[base + s * rs] : mk(T(0), T(0));
+  for (int s = 0; s < M; ++s) d[s] = (ok && own && j0 + s < ny) ? fin[base + s * rs] : mk(T(0), T(0));
   __syncthreads();  // coefficients staged
   if (own) {
     T v[M], w[M];
@@ -273,7 +279,8 @@ k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
   }
   if (ok && own && !is_special(kx, kz, ya.nz, ya.skip_kx, ya.skip_kz)) {
 #pragma unroll
-    for (int s = 0; s < M; ++s) pout[base + s * rs] = d[s];
+    for (int s = 0; s < M; ++s)
+      if (j0 + s < ny) pout[base + s * rs] = d[s];
   }
 }
 

@@ -36,10 +36,11 @@ int ysolve_default_lb(int P, int M) {
 }
 
 template <typename T, int M, int MODE, bool DROP>
-static hipError_t ysolve_go(long blocks, const int* blist, const YArgs& ya, int threads, int ny, const cx<T>* fin,
+static hipError_t ysolve_go(long blocks, const int* blist, const YArgs& ya, int threads, const cx<T>* fin,
                             cx<T>* pout, const T* a, const T* c, const T* kx2, const T* kz2, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  const size_t lds = MODE == kSlabLocal ? sizeof(T) * 2 * (size_t)ny : ysolve_lds_bytes<T>(ny, ya.P, ya.LB, DROP);
+  const int nyp = ya.P * M;  // rows of the partitions (padded past ny)
+  const size_t lds = MODE == kSlabLocal ? sizeof(T) * 2 * (size_t)nyp : ysolve_lds_bytes<T>(nyp, ya.P, ya.LB, DROP);
   hipLaunchKernelGGL((k_ysolve<T, M, MODE, DROP>), dim3(blocks), dim3(threads), lds, s, fin, pout, a, c, kx2, kz2,
                      blist, ya);
   return hipGetLastError();
@@ -49,7 +50,7 @@ template <typename T, int M>
 static hipError_t ysolve_m(const YLaunch& y, const YArgs& ya, int threads, const cx<T>* fin, cx<T>* pout, const T* a,
                            const T* c, const T* kx2, const T* kz2, hipStream_t s) {
   const long all = (y.nlines + ya.LB - 1) / ya.LB;
-  if (y.mode == kSlabLocal) return ysolve_go<T, M, kSlabLocal, false>(all, nullptr, ya, threads, y.ny, fin, pout, a, c,
+  if (y.mode == kSlabLocal) return ysolve_go<T, M, kSlabLocal, false>(all, nullptr, ya, threads, fin, pout, a, c,
                                                                       kx2, kz2, s);
   // blocks whose lines all allow the drop take the dropped reduced system, the
   // others the exact one (two launches over the plan's block lists; without
@@ -57,13 +58,13 @@ static hipError_t ysolve_m(const YLaunch& y, const YArgs& ya, int threads, const
   const long ne = y.blocks_exact ? y.n_exact : all;
   hipError_t e;
   if (y.mode == kSlabFinish) {
-    e = ysolve_go<T, M, kSlabFinish, false>(ne, y.blocks_exact, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+    e = ysolve_go<T, M, kSlabFinish, false>(ne, y.blocks_exact, ya, threads, fin, pout, a, c, kx2, kz2, s);
     if (e == hipSuccess && y.blocks_drop)
-      e = ysolve_go<T, M, kSlabFinish, true>(y.n_drop, y.blocks_drop, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+      e = ysolve_go<T, M, kSlabFinish, true>(y.n_drop, y.blocks_drop, ya, threads, fin, pout, a, c, kx2, kz2, s);
   } else {
-    e = ysolve_go<T, M, kWhole, false>(ne, y.blocks_exact, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+    e = ysolve_go<T, M, kWhole, false>(ne, y.blocks_exact, ya, threads, fin, pout, a, c, kx2, kz2, s);
     if (e == hipSuccess && y.blocks_drop)
-      e = ysolve_go<T, M, kWhole, true>(y.n_drop, y.blocks_drop, ya, threads, y.ny, fin, pout, a, c, kx2, kz2, s);
+      e = ysolve_go<T, M, kWhole, true>(y.n_drop, y.blocks_drop, ya, threads, fin, pout, a, c, kx2, kz2, s);
   }
   return e;
 }
@@ -118,10 +119,10 @@ hipError_t launch_ysolve(const YLaunch& y, const cx<T>* fin, cx<T>* pout, const 
   return hipErrorInvalidValue;
 }
 
-// Dynamic LDS needed by a y-solve launch (checked by the plan against the
-// device limit).
-size_t ysolve_lds_needed(int ny, int P, int LB, bool fp64) {
-  return fp64 ? ysolve_lds_bytes<double>(ny, P, LB, true) : ysolve_lds_bytes<float>(ny, P, LB, true);
+// Dynamic LDS needed by a y-solve launch over P partitions of nyp / P rows
+// (checked by the plan against the device limit).
+size_t ysolve_lds_needed(int nyp, int P, int LB, bool fp64) {
+  return fp64 ? ysolve_lds_bytes<double>(nyp, P, LB, true) : ysolve_lds_bytes<float>(nyp, P, LB, true);
 }
 
 template <typename T>

@@ -61,7 +61,7 @@ def _create(nx, ny, nz, yf, opt=None, lx=1.0, lz=1.0):
     (16, 8, 18, "nz = 18 (two factors of 3)", L.CF_ERR_UNSUPPORTED),
     (8192, 8, 8, "nx/2 above 2048", L.CF_ERR_UNSUPPORTED),
     (16, 1, 8, "ny = 1", L.CF_ERR_ARG),
-    (16, 130, 8, "ny = 130 = 2*5*13 has no partitioning", L.CF_ERR_UNSUPPORTED),
+    (16, 1031, 8, "ny = 1031 needs more than 64 partitions of at most 16 rows (FP64)", L.CF_ERR_UNSUPPORTED),
 ])
 def test_plan_rejects_bad_sizes(nx, ny, nz, why, code):
     yf = np.linspace(-1, 1, max(ny, 1) + 1)
@@ -86,7 +86,7 @@ def test_plan_rejects_bad_grid_and_options():
     opt.precision = 7
     assert _create(16, 8, 8, yf, opt)[0] == L.CF_ERR_ARG
     L.lib().cf_options_default(C.byref(opt))
-    opt.n_parts = 3  # 8 rows do not split into 3 partitions
+    opt.n_parts = 5  # 5 partitions of ceil(8/5) = 2 rows: the fifth would hold only padding
     assert _create(16, 8, 8, yf, opt)[0] == L.CF_ERR_UNSUPPORTED
     L.lib().cf_options_default(C.byref(opt))
     opt.precision = L.CF_MIXED

@@ -26,7 +26,7 @@ def plans(nx, ny, nz, gamma, lx, lz, **kw):
 
 
 @pytest.mark.parametrize("nx,ny,nz,gamma", [(64, 64, 64, 2.0), (256, 128, 192, 2.6), (96, 48, 24, 2.5),
-                                              (2048, 16, 24, 2.0)])
+                                              (2048, 16, 24, 2.0), (64, 130, 48, 2.5)])
 def test_mixed_poisson_refinement(nx, ny, nz, gamma):
     """RHS = divergence of a seeded field with a k^-5/3-like horizontal spectrum
     (the mixed-precision workload's recipe).  One FP64 residual + correction

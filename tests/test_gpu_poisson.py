@@ -23,6 +23,12 @@ CASES = [
     # long x rows: 8 (FP64) rows per x-transform block, a ragged last block in z
     (2048, 8, 12, 2.0, 0),
     (4096, 8, 6, 1.5, 0),
+    # P not dividing ny: the last partition padded (130 = 11*12 - 2 automatic,
+    # 97 = 13*8 - 7 automatic, 8 = 3*3 - 1, 250 = 16*16 - 6)
+    (64, 130, 32, 2.5, 0),
+    (48, 97, 24, 2.0, 0),
+    (32, 8, 16, 2.0, 3),
+    (64, 250, 16, 2.5, 16),
 ]
 
 

@@ -34,7 +34,9 @@ def spectrum(pl, seed, dtype):
 
 # (nx, ny, nz, gamma, n_parts): ragged line counts, radix-3 partition counts
 CASES = [(64, 64, 64, 2.0, 4), (128, 128, 96, 2.0, 8), (96, 36, 24, 2.5, 3), (256, 96, 48, 2.5, 6),
-         (48, 24, 12, 2.0, 2)]
+         (48, 24, 12, 2.0, 2),
+         # padded last partition: 130 rows in 22 partitions of 6, 97 in 13 of 8
+         (64, 130, 32, 2.5, 22), (48, 97, 24, 2.0, 13)]
 
 
 @pytest.mark.parametrize("nx,ny,nz,gamma,parts", CASES)

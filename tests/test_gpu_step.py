@@ -19,6 +19,8 @@ CASES = [
     # partial x and z tiles of the RK kernels and y-chunks with a ragged last one
     (96, 70, 12, 2.0, 1e-3, 1 / 550),
     (96, 136, 24, 2.5, 1e-3, 1 / 550),
+    # ny = 130: 11 partitions of 12 rows, the last one padded by two
+    (64, 130, 32, 2.5, 1e-3, 1 / 550),
 ]
 
 

@@ -24,9 +24,14 @@ def rel(a, b):
 
 
 def admissible(ny, mixed=False):
+    """(P, lines per block) candidates: P partitions that divide ny into a
+    compiled row count; if none does, P partitions of ceil(ny/P) compiled rows
+    with every partition holding a row of the line (the last one padded)."""
     ms = M_SET_FP32 if mixed else M_SET
-    return {(P, lb) for P in range(1, 65) if ny % P == 0 and ny // P in ms
-            for lb in (4, 8, 16, 32, 64, 128, 256) if 64 <= lb * P <= 512}
+    ps = [P for P in range(1, 65) if ny % P == 0 and ny // P in ms]
+    if not ps:
+        ps = [P for P in range(1, 65) if -(-ny // P) in ms and (P - 1) * -(-ny // P) < ny]
+    return {(P, lb) for P in ps for lb in (4, 8, 16, 32, 64, 128, 256) if 64 <= lb * P <= 512}
 
 
 def make(nx, ny, nz, gamma, **kw):
@@ -46,7 +51,7 @@ def test_tuned_partitioning_fp64(nx, ny, nz, gamma):
     info = pl.info()
     best = min(rows, key=lambda r: r[2])
     assert (info["n_parts"], info["lines_per_block"]) == best[:2]
-    assert info["rows_per_part"] * info["n_parts"] == ny
+    assert info["rows_per_part"] * info["n_parts"] == ny   # a partitioning that divides ny exists
     f = synth.uniform_rhs(nx, ny, nz, seed=3)
     p = pl.poisson_solve(torch.tensor(f, device=dev())).cpu().numpy()
     p_ref = O.poisson(torch.tensor(f), box).numpy()
@@ -55,6 +60,24 @@ def test_tuned_partitioning_fp64(nx, ny, nz, gamma):
     assert same.partition_timings() == []
     q = same.poisson_solve(torch.tensor(f, device=dev())).cpu().numpy()
     assert np.array_equal(p, q)
+
+
+def test_tuned_partitioning_padded():
+    """ny = 130 has no partitioning into a compiled row count: the candidates
+    are the padded ones (M = ceil(130/P)), and the tuned plan meets the
+    oracle."""
+    nx, ny, nz = 64, 130, 32
+    pl, box = make(nx, ny, nz, 2.5, tune_parts=True)
+    rows = pl.partition_timings()
+    got = {(P, lb) for P, lb, _ in rows}
+    assert got <= admissible(ny) and len(got) >= 2
+    info = pl.info()
+    assert (info["n_parts"], info["lines_per_block"]) == min(rows, key=lambda r: r[2])[:2]
+    M, Pn = info["rows_per_part"], info["n_parts"]
+    assert (Pn - 1) * M < ny < Pn * M
+    f = synth.uniform_rhs(nx, ny, nz, seed=6)
+    p = pl.poisson_solve(torch.tensor(f, device=dev())).cpu().numpy()
+    assert rel(p, O.poisson(torch.tensor(f), box).numpy()) <= 1e-12
 
 
 @pytest.mark.parametrize("lb", [4, 8, 16, 32])

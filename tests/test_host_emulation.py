@@ -79,6 +79,43 @@ def test_pdd_exact_matches_thomas(H, ny, Pn, k2):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("ny,Pn", [(130, 11), (97, 13), (250, 16), (7, 2), (1000, 63), (61, 8)])
+@pytest.mark.parametrize("k2", [0.25, 7.0, 3000.0])
+def test_padded_partitions_match_thomas(H, ny, Pn, k2):
+    """ny not a multiple of P: partitions of M = ceil(ny/P) rows, the last one
+    completed by zero rows (a = c = 0, zero right-hand side) past the wall row.
+    The exact PDD (cyclic reduction of the reduced system) and the one-group
+    grouped form both reproduce Thomas on the ny real rows (to a bound that
+    grows with ny: the low-k^2 lines' conditioning, the same with and without
+    padding, e.g. 1.4e-11 relative at ny = 1000 and 2.3e-11 at ny = 1008 = 63*16
+    for k^2 = 0.25)."""
+    tol = max(1e-11, 5e-14 * ny)
+    a, c = _line_system(ny, 2.5, k2)
+    rng = np.random.default_rng(ny * Pn)
+    d = rng.standard_normal(ny) + 1j * rng.standard_normal(ny)
+    di = np.ascontiguousarray(np.stack([d.real, d.imag], -1).reshape(-1))
+    b = -(a + c) - k2
+    ref = O.thomas(torch.tensor(a), torch.tensor(b), torch.tensor(c), torch.tensor(d)).numpy()
+    x = np.zeros(2 * ny)
+    assert H.cfh_pdd_line(ny, Pn, P(a), P(c), k2, 1, 0, P(di), P(x)) == 0
+    got = x[0::2] + 1j * x[1::2]
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    x[:] = 0
+    assert H.cfh_pdd_line_grouped(ny, Pn, 1, P(a), P(c), k2, 0, P(di), P(x)) == 0
+    got = x[0::2] + 1j * x[1::2]
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("ny,Pn", [(17, 16), (100, 64), (5, 4)])
+def test_partitionings_with_an_empty_part_are_rejected(H, ny, Pn):
+    """(P-1) * ceil(ny/P) >= ny leaves the last partition without a row of the
+    line (only padding): such a partitioning is refused."""
+    a, c = _line_system(max(ny, 2), 2.5, 1.0)
+    di = np.zeros(2 * ny)
+    x = np.zeros(2 * ny)
+    assert H.cfh_pdd_line(ny, Pn, P(a), P(c), 1.0, 1, 0, P(di), P(x)) == 1
+
+
 @pytest.mark.parametrize("ny,Pn", [(64, 4), (256, 16), (96, 8)])
 def test_pdd_drop_matches_oracle_pdd(H, ny, Pn):
     a, c = _line_system(ny, 2.0, 0)
