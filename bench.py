@@ -141,6 +141,30 @@ def summarize_trace(path):
     return "\n".join(out)
 
 
+def summarize_trace_last(path, n):
+    """Markdown table of the mean duration of each kernel's last n dispatches
+    in a rocprofv3 run_kernel_trace.csv (the timed launches of a run whose
+    first dispatches are warm-up)."""
+    import collections
+    import csv
+    import re
+    runs = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+        runs[k].append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    out = [f"| kernel | launches | avg us (last {n}) |", "|---|---:|---:|"]
+    rows = []
+    for k, v in runs.items():
+        if not k.startswith("cf::"):
+            continue
+        v.sort()
+        last = v[-n:]
+        rows.append((sum(e - b for b, e in last) / len(last) / 1e3, k, len(v)))
+    for us, k, c in sorted(rows, reverse=True):
+        out.append(f"| `{k}` | {c} | {us:.1f} |")
+    return "\n".join(out)
+
+
 def copy_bandwidth(nbytes: int = 1 << 30, reps: int = 20) -> float:
     """Device-to-device bandwidth of a plain elementwise kernel (torch.add,
     reading and writing nbytes each), the practical ceiling the kernels' GB/s
@@ -683,6 +707,9 @@ def main():
                     help="time the Poisson solve alone instead of the projection step")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="print the traffic table of rocprofv3 --pmc passes and exit")
     ap.add_argument("--summarize-trace", metavar="CSV", help="print a rocprofv3 kernel_stats.csv as markdown and exit")
+    ap.add_argument("--trace-last", type=int, default=0, metavar="N",
+                    help="with --summarize-trace on a run_kernel_trace.csv: the mean of each kernel's last N "
+                         "dispatches")
     ap.add_argument("--profile-fwd-adjoint", type=int, default=0, metavar="STEPS",
                     help="only run STEPS FP64 forward + adjoint steps on the step grid (for a profiler) and exit")
     ap.add_argument("--profile-fwd-adjoint-mixed", action="store_true",
@@ -701,7 +728,8 @@ def main():
         print(summarize_pmc(args.summarize_pmc))
         return
     if args.summarize_trace:
-        print(summarize_trace(args.summarize_trace))
+        print(summarize_trace_last(args.summarize_trace, args.trace_last) if args.trace_last
+              else summarize_trace(args.summarize_trace))
         return
     if args.source_hash:
         print(kernel_source_hash(args.source_hash))
