@@ -54,6 +54,12 @@ KERNEL_SOURCES = {
     "fft_z_fwd": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
     "fft_z_inv": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip"],
     "ysolve": ["cf_common.h", "cf_pdd.h", "cf_ysolve_kernels.h", "cf_ysolve_launch.hip"],
+    # whole paths: every kernel source they launch and the plan that sequences them
+    "step_fp64": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip", "cf_pdd.h",
+                  "cf_ysolve_kernels.h", "cf_ysolve_launch.hip", "cf_step_kernels.h", "cf_rk_fused.h",
+                  "cf_step_launch.hip", "cf_plan.hip"],
+    "poisson_mixed": ["cf_common.h", "cf_fft.h", "cf_fft_kernels.h", "cf_fft_launch.hip", "cf_pdd.h",
+                      "cf_ysolve_kernels.h", "cf_ysolve_launch.hip", "cf_plan.hip"],
 }
 
 
@@ -76,10 +82,10 @@ def kernel_source_hash(kernel: str) -> str | None:
 
 
 def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` on `workload` from the counter summaries
-    in profiles/ (rocprofv3 FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled
-    by the factors a plain copy kernel gives), or None when no summary was taken
-    on the kernel's current source."""
+    """HBM bytes per launch of `kernel` (or per step / solve of a whole path) on
+    `workload` from the counter summaries in profiles/ (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, KiB, scaled by the factors a plain copy kernel gives), or None
+    when no summary was taken on the current source."""
     import glob
     want = kernel_source_hash(kernel)
     for path in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.txt")):
@@ -127,6 +133,32 @@ def summarize_pmc(base):
         f, w = fe[(k, "FETCH_SIZE")], wr.get((k, "WRITE_SIZE"), float("nan"))
         out.append(f"| `{k}` | {f:.0f} | {w:.0f} | {f * f_fac * 1024 / 1e9:.3f} | {w * w_fac * 1024 / 1e9:.3f} |")
     return "\n".join(out)
+
+
+def pmc_record(base, name, workload, units, exclude=()):
+    """Traffic record (the key: value form measured_traffic reads) of a whole
+    path: FETCH_SIZE and WRITE_SIZE summed over every dispatch of a cf:: kernel
+    in the passes fetch/ and write/ under `base`, divided by the number of
+    steps or solves (`units`) the profiled run made; kernels whose name
+    contains a string in `exclude` (input generation) are left out.  Scaling
+    factors from the copy_fetch/ and copy_write/ calibration passes."""
+    import csv
+    import re
+    cf, cw = _pmc_load(base, "copy_fetch"), _pmc_load(base, "copy_write")
+    copy = [k for (k, c) in cf if "CUDAFunctor" in k][0]
+    kib = 1024 * 1024
+
+    def total(pas, counter):
+        t = 0.0
+        for r in csv.DictReader(open(f"{base}/{pas}/run_counter_collection.csv")):
+            k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            if r["Counter_Name"] == counter and k.startswith("cf::") and not any(e in k for e in exclude):
+                t += float(r["Counter_Value"])
+        return t / units
+    return "\n".join([f"kernel: {name}", f"workload: {workload}", f"source_sha256: {kernel_source_hash(name)}",
+                      f"fetch_kib: {total('fetch', 'FETCH_SIZE'):.0f}", f"write_kib: {total('write', 'WRITE_SIZE'):.0f}",
+                      f"fetch_factor: {kib / cf[(copy, 'FETCH_SIZE')]:.3f}",
+                      f"write_factor: {kib / cw[(copy, 'WRITE_SIZE')]:.3f}"])
 
 
 def summarize_trace(path):
@@ -559,9 +591,12 @@ def secondary(wl, steps):
     torch.cuda.empty_cache()
     pb = torch.empty_like(fb)
     t = _time(lambda: pm.poisson_solve(fb, out=pb), max(2, steps // 2), warmup=1)
+    ctr = measured_traffic("poisson_mixed", "mixed1000")
     res["poisson_mixed_refine1_2048x512x1536"] = _leg(
         "poisson_mixed_refine1", (big.nx, big.ny, big.nz), t,
-        input="f = D u of the k^-5/3 power-law field (seed 0, generated on the device)")
+        input="f = D u of the k^-5/3 power-law field (seed 0, generated on the device)",
+        counter_bytes=ctr, counter_GBps=round(ctr / t / 1e9, 1) if ctr else None,
+        counter_hbm_frac=round(ctr / t / 1e9 / HBM_PEAK_GBS, 4) if ctr else None)
     # the same right-hand side solved in FP64 (the metric's FP64 vs FP32+refine)
     p64 = Plan(big.nx, big.ny, big.nz, big.lx, big.lz, big.y_faces(), precision="fp64")
     t = _time(lambda: p64.poisson_solve(fb, out=pb), max(2, steps // 2), warmup=1)
@@ -707,6 +742,11 @@ def main():
                     help="time the Poisson solve alone instead of the projection step")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="print the traffic table of rocprofv3 --pmc passes and exit")
     ap.add_argument("--summarize-trace", metavar="CSV", help="print a rocprofv3 kernel_stats.csv as markdown and exit")
+    ap.add_argument("--pmc-record", nargs=4, metavar=("DIR", "NAME", "WORKLOAD", "UNITS"),
+                    help="print the traffic record of a whole path (step_fp64, poisson_mixed) from the counter "
+                         "passes under DIR, per one of the UNITS steps or solves the profiled run made, and exit")
+    ap.add_argument("--pmc-exclude", nargs="*", default=[], metavar="NAME",
+                    help="with --pmc-record: kernels (name substrings) to leave out, e.g. input generation")
     ap.add_argument("--trace-last", type=int, default=0, metavar="N",
                     help="with --summarize-trace on a run_kernel_trace.csv: the mean of each kernel's last N "
                          "dispatches")
@@ -726,6 +766,10 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
+        return
+    if args.pmc_record:
+        d, name, workload, units = args.pmc_record
+        print(pmc_record(d, name, workload, int(units), args.pmc_exclude))
         return
     if args.summarize_trace:
         print(summarize_trace_last(args.summarize_trace, args.trace_last) if args.trace_last
@@ -814,6 +858,7 @@ def main():
     model_bytes = sum(kb(k) * v[1] for k, v in kern.items()) / args.steps
     what = "FP64 pressure-Poisson solve" if args.poisson_only else "FP64 projection step (RK2 + Poisson + correction)"
     traffic = measured_traffic(dom, wl.name) if not args.poisson_only else None
+    step_traffic = measured_traffic("step_fp64", wl.name) if not args.poisson_only else None
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -838,6 +883,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes": nbytes},
         "model_GBps_whole_step": round(model_bytes / (ms * 1e-3) / 1e9, 1),
         "hbm_frac_whole_step": round(model_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # counter-measured bytes of one step (all its kernels) over this run's step time
+        "counter_GBps_whole_step": (round(step_traffic / (ms * 1e-3) / 1e9, 1) if step_traffic else None),
         "measured_copy_GBps": copy_bandwidth(),
         "kernels": per_kernel,
     }
