@@ -274,8 +274,9 @@ def cpu_baseline(wl, poisson_only: bool):
     seeded arrays the GPU line times (about 20-30 s on 16 host threads).  Also:
     one thread on a bounded sample of the same recipe (the workload's x-z planes
     with ny reduced to 16, its own tanh grid; mean of two calls), the 64^3
-    Poisson solve and the 256x128x256 step (whole grids, all threads), and the
-    host's core count and CPU model."""
+    Poisson solve and the 256x128x256 step (whole grids, all threads), the
+    Poisson solve on 192 z-planes of the 2048x512x1536 grid, and the host's
+    core count and CPU model."""
     import torch
 
     import oracle as O
@@ -326,6 +327,19 @@ def cpu_baseline(wl, poisson_only: bool):
     u4, v4, w4f = (torch.tensor(q) for q in synth.perturbed_poiseuille(w4.nx, w4.ny, w4.nz, y4, seed=0))
     out["step_fp64_256x128x256"], _ = _oracle_rate(
         lambda: O.projection_step(u4, v4, w4f, b4, w4.dt, w4.nu, w4.fx), w4.nx * w4.ny * w4.nz, max_calls=1)
+    del u4, v4, w4f
+    # the 2048x512x1536 mixed workload's x-y planes with nz reduced to 192: the
+    # FP64 oracle Poisson solve (the oracle has no mixed precision; the whole
+    # grid would take minutes), all threads
+    w3 = synth.WORKLOADS["mixed1000"]
+    nz3 = 192
+    b3 = O.Box(w3.nx, w3.ny, nz3, w3.lx, w3.lz * nz3 / w3.nz, w3.y_faces())
+    f3 = torch.tensor(synth.uniform_rhs(w3.nx, w3.ny, nz3, seed=0))
+    r3, n3 = _oracle_rate(lambda: O.poisson(f3, b3), w3.nx * w3.ny * nz3, max_calls=1, warm=False)
+    out["poisson_fp64_2048x512x192"] = {"value": r3, "calls": n3,
+                                       "sample": f"{w3.nx}x{w3.ny}x{nz3}: the {w3.nx}x{w3.ny}x{w3.nz} "
+                                                 f"workload's x-y planes (its tanh grid), nz reduced to {nz3}"}
+    del f3
     out["host"] = _host_info()
     out["host"]["torch_threads"] = threads
     return out
