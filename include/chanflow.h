@@ -154,9 +154,11 @@ cf_status cf_plan_tuning(const cf_plan* plan, int cap, int* count, int* parts, i
  * p = the unique solution of L_h p = f - mean_W(f) with mean_W(p) = 0, where
  * L_h = D o G is the staggered 7-point Laplacian (Neumann walls) and
  * mean_W(q) = sum_j dy_j q_j / (nx nz sum_j dy_j).
- * f, p: device double arrays (ny, nz, nx); p may alias f.
+ * f, p: device double arrays (ny, nz, nx); p may be f itself (in place) but
+ * must not overlap it otherwise (CF_ERR_ARG).
  * CF_MIXED plans compute in FP32 with FP64 low-wavenumber lines and the FP64
- * residual-correction passes of the plan; f and p stay double.
+ * residual-correction passes of the plan; f and p stay double (while the solve
+ * runs, p holds intermediate values).
  */
 cf_status cf_poisson_solve(cf_plan* plan, const double* f, double* p, void* stream);
 

@@ -1305,6 +1305,13 @@ cf_status cf_poisson_solve(cf_plan* pl, const double* f, double* p, void* stream
   CF_TRY(check_plan(pl));
   CF_TRY(check_ptr(f, "f"));
   CF_TRY(check_ptr(p, "p"));
+  {
+    // p is f itself or disjoint from it: a mixed solve reads f again after
+    // writing p (the residual), so a partial overlap would read overwritten f
+    const uintptr_t bytes = (uintptr_t)pl->nx * pl->ny * pl->nz * sizeof(double);
+    const uintptr_t a = reinterpret_cast<uintptr_t>(f), b = reinterpret_cast<uintptr_t>(p);
+    if (a != b && a < b + bytes && b < a + bytes) return fail(CF_ERR_ARG, "p must be f itself or not overlap it");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->mixed()) return poisson_mixed(pl, MixedRhs{0, f, nullptr, nullptr, nullptr, 1.0}, p, s);
   return poisson_t<double>(pl, f, p, s);

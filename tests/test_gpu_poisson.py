@@ -229,6 +229,28 @@ def test_bad_tensor_arguments_rejected():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_partially_overlapping_output_rejected(precision):
+    """p may be f itself, but an output that overlaps f at another offset is
+    refused before anything runs (a mixed solve reads f again after writing
+    p), and f is left untouched."""
+    from paper_2104_08863_amd._lib import ChanflowError
+    nx, ny, nz = 32, 16, 8
+    pl, box = plan_for(nx, ny, nz, 2.0, precision=precision)
+    n = nx * ny * nz
+    buf = torch.zeros(2 * n, dtype=torch.float64, device=dev())
+    f = buf[:n].view(ny, nz, nx)
+    f.copy_(torch.tensor(synth.uniform_rhs(nx, ny, nz, seed=5), device=dev()))
+    keep = f.clone()
+    for off in (2, n // 2, n - 2):
+        with pytest.raises(ChanflowError):
+            pl.poisson_solve(f, out=buf[off:off + n].view(ny, nz, nx))
+    assert torch.equal(f, keep)
+    p = pl.poisson_solve(f, out=buf[n:].view(ny, nz, nx))   # disjoint: fine
+    q = pl.poisson_solve(f.clone())
+    assert torch.equal(p, q)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_non_finite_right_hand_side_is_reported(precision):
     """A NaN or an infinity anywhere in f reaches the kx = kz = 0 line of its
     plane; the solve flags it and cf_plan_numeric_status returns CF_ERR_NUMERIC
