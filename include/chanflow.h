@@ -177,8 +177,10 @@ cf_status cf_divergence(cf_plan* plan, const double* u, const double* v, const d
  * so that D u1 = 0 to round-off.  N(u) = div(u u) in flux form (linear interpolation,
  * the y-interpolation to a face weighted by the two cell heights); lap uses the no-slip
  * ghost mirrored about the wall; v = 0 on both walls.
- * u, v, w: device inputs (ny, nz, nx); u1, v1, w1: outputs (may alias the inputs);
- * p: device double output (ny, nz, nx) or NULL (pressure kept in the plan workspace).
+ * u, v, w: device inputs (ny, nz, nx); u1, v1, w1: outputs (may alias the inputs,
+ * must not overlap each other); p: device double output (ny, nz, nx), not
+ * overlapping any velocity array, or NULL (pressure kept in the plan workspace).
+ * Overlaps that are not allowed return CF_ERR_ARG before anything runs.
  * Velocity arrays are double for CF_FP64 plans and float for CF_MIXED plans.
  * The plan must have been created with CF_PLAN_STEP in opt->flags.
  */

@@ -420,6 +420,12 @@ cf_status check_plan(const cf_plan* pl) {
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+// Whether the byte ranges [a, a + na) and [b, b + nb) share a byte.
+bool bytes_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
 cf_status check_ptr(const void* p, const char* name) {
   if (!p) return fail(CF_ERR_ARG, std::string(name) + " is NULL");
   if (!aligned16(p)) return fail(CF_ERR_ARG, std::string(name) + " is not 16-byte aligned");
@@ -1345,6 +1351,21 @@ cf_status cf_projection_step(cf_plan* pl, const void* u, const void* v, const vo
   if (p) CF_TRY(check_ptr(p, "p"));
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(CF_ERR_ARG, "dt must be finite and > 0");
   if (!(nu >= 0.0) || !std::isfinite(nu) || !std::isfinite(fx)) return fail(CF_ERR_ARG, "nu >= 0 and fx must be finite");
+  {
+    // the outputs are written while the others are still read: u1, v1, w1
+    // pairwise disjoint, and p disjoint from all six velocity arrays
+    const size_t nb = (size_t)pl->nx * pl->ny * pl->nz * (pl->mixed() ? sizeof(float) : sizeof(double));
+    const void* outs[3] = {u1, v1, w1};
+    for (int a = 0; a < 3; ++a)
+      for (int b = a + 1; b < 3; ++b)
+        if (bytes_overlap(outs[a], nb, outs[b], nb)) return fail(CF_ERR_ARG, "u1, v1, w1 must not overlap");
+    if (p) {
+      const size_t pb = (size_t)pl->nx * pl->ny * pl->nz * sizeof(double);
+      const void* vel[6] = {u, v, w, u1, v1, w1};
+      for (const void* q : vel)
+        if (bytes_overlap(p, pb, q, nb)) return fail(CF_ERR_ARG, "p must not overlap the velocity arrays");
+    }
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->mixed())
     return step_mixed(pl, static_cast<const float*>(u), static_cast<const float*>(v), static_cast<const float*>(w),

@@ -82,6 +82,29 @@ def test_projection_step_in_place_and_repeatable():
         assert torch.equal(x, y)
 
 
+def test_overlapping_step_outputs_rejected():
+    """Two velocity outputs in the same memory, or a pressure output inside a
+    velocity array, are refused before anything runs; the inputs are left
+    untouched."""
+    from paper_2104_08863_amd._lib import ChanflowError
+    nx, ny, nz = 32, 16, 24
+    pl, box = setup(nx, ny, nz, 2.0)
+    u, v, w = (torch.tensor(q, device=dev()) for q in synth.perturbed_poiseuille(nx, ny, nz, box.y_faces, seed=0))
+    keep = [q.clone() for q in (u, v, w)]
+    a, b = torch.empty_like(u), torch.empty_like(u)
+    with pytest.raises(ChanflowError):
+        pl.projection_step(u, v, w, 1e-3, 1 / 550, 3 / 550, out=(a, a, b))
+    buf = torch.empty(2 * u.numel(), dtype=torch.float64, device=dev())
+    u1 = buf[:u.numel()].view_as(u)
+    with pytest.raises(ChanflowError):
+        pl.projection_step(u, v, w, 1e-3, 1 / 550, 3 / 550, out=(u1, a, b),
+                           p=buf[u.numel() // 2:u.numel() // 2 + u.numel()].view_as(u))
+    with pytest.raises(ChanflowError):
+        pl.projection_step(u, v, w, 1e-3, 1 / 550, 3 / 550, out=(a, b, torch.empty_like(u)), p=v)
+    for q, k in zip((u, v, w), keep):
+        assert torch.equal(q, k)
+
+
 def test_step_needs_step_workspace():
     from paper_2104_08863_amd.api import Plan
     from paper_2104_08863_amd._lib import ChanflowError
