@@ -165,7 +165,8 @@ cf_status cf_poisson_solve(cf_plan* plan, const double* f, double* p, void* stre
 /*
  * Divergence right-hand side (Eq. (7), Section 3.2 step (1)):
  * f = scale * [ (u_i - u_{i-1})/dx + (v_j - v_{j-1})/dy_j + (w_k - w_{k-1})/dz ],
- * v = 0 on both walls.  u, v, w, f: device double arrays (ny, nz, nx).
+ * v = 0 on both walls.  u, v, w, f: device double arrays (ny, nz, nx); f must not
+ * overlap u, v or w (CF_ERR_ARG).
  */
 cf_status cf_divergence(cf_plan* plan, const double* u, const double* v, const double* w,
                         double* f, double scale, void* stream);
@@ -205,7 +206,8 @@ cf_status cf_rk2_predictor(cf_plan* plan, const void* u, const void* v, const vo
  * stored u, v, w and of their squares, summed in FP64:
  *   stats[6 j + 0..2] = <u>_j, <v>_j, <w>_j,  stats[6 j + 3..5] = <u^2>_j, <v^2>_j, <w^2>_j
  * (v's plane j is the face above cell j; its top-wall plane is taken as stored).
- * u, v, w as in cf_projection_step; stats: device double (ny, 6), overwritten.
+ * u, v, w as in cf_projection_step; stats: device double (ny, 6), overwritten, not
+ * overlapping u, v or w (CF_ERR_ARG).
  * Bitwise repeatable (fixed reduction order, no atomics).
  */
 cf_status cf_plane_stats(cf_plan* plan, const void* u, const void* v, const void* w, double* stats,
@@ -253,7 +255,8 @@ cf_status cf_projection_step_adjoint(cf_plan* plan, const void* u, const void* v
                                      void* gv, void* gw, double dt, double nu, double fx, void* stream);
 
 /* Test hook: (gu, gv, gw) = J_R(u, v, w)^T (lu, lv, lw), the transpose of the momentum
- * right-hand side's Jacobian at (u, v, w).  Arrays as in cf_projection_step. */
+ * right-hand side's Jacobian at (u, v, w).  Arrays as in cf_projection_step; gu, gv,
+ * gw must not overlap each other or any input (CF_ERR_ARG). */
 cf_status cf_rhs_adjoint(cf_plan* plan, const void* u, const void* v, const void* w, const void* lu,
                          const void* lv, const void* lw, void* gu, void* gv, void* gw, double nu,
                          void* stream);
@@ -269,7 +272,8 @@ cf_status cf_inverse_spectral(cf_plan* plan, const void* phat, double* p, void* 
 
 /* Test hook, step (5): solve every wall-normal line of fhat (Eq. (9) with the PDD of
  * Section 2.2, exact or dropped reduced system per the plan, gauge on the kx=kz=0 line)
- * into phat.  Same layout and precision as cf_forward_spectral; phat may alias fhat. */
+ * into phat.  Same layout and precision as cf_forward_spectral; phat may be fhat
+ * itself but must not overlap it otherwise (CF_ERR_ARG). */
 cf_status cf_solve_spectral(cf_plan* plan, const void* fhat, void* phat, void* stream);
 
 /*
@@ -285,7 +289,8 @@ cf_status cf_solve_spectral(cf_plan* plan, const void* fhat, void* phat, void* s
  * would be the devices and iface the buffer they exchange; here the slabs run
  * one after another on one device.  The result equals cf_solve_spectral's
  * bitwise.  iface: device buffer of cf_plan_info.slab_iface_bytes (layout
- * [n_parts][8][n_lines], plan precision), overwritten.  phat may alias fhat.
+ * [n_parts][8][n_lines], plan precision), overwritten.  phat may be fhat itself but
+ * must not overlap it otherwise (CF_ERR_ARG).
  * Not available with CF_PLAN_Y_DCT (no partitions).
  */
 cf_status cf_solve_spectral_slabs(cf_plan* plan, int n_slabs, const void* fhat, void* phat, void* iface,

@@ -426,6 +426,20 @@ bool bytes_overlap(const void* a, size_t na, const void* b, size_t nb) {
   return x < y + nb && y < x + na;
 }
 
+// CF_ERR_ARG when output `out` (nout bytes) overlaps input `in` (nin bytes),
+// unless same_ok and out is in itself.
+cf_status check_disjoint(const void* out, size_t nout, const void* in, size_t nin, bool same_ok, const char* what) {
+  if (same_ok && out == in) return CF_OK;
+  if (bytes_overlap(out, nout, in, nin)) return fail(CF_ERR_ARG, what);
+  return CF_OK;
+}
+
+// Bytes of a physical field and of a spectrum of the plan.
+size_t field_bytes(const cf_plan* pl, size_t esize) { return (size_t)pl->nx * pl->ny * pl->nz * esize; }
+size_t spec_bytes(const cf_plan* pl) {
+  return (size_t)pl->nkx * pl->ny * pl->nz * (pl->mixed() ? sizeof(cx<float>) : sizeof(cx<double>));
+}
+
 cf_status check_ptr(const void* p, const char* name) {
   if (!p) return fail(CF_ERR_ARG, std::string(name) + " is NULL");
   if (!aligned16(p)) return fail(CF_ERR_ARG, std::string(name) + " is not 16-byte aligned");
@@ -1261,6 +1275,7 @@ cf_status cf_solve_spectral(cf_plan* pl, const void* fhat, void* phat, void* str
   CF_TRY(check_plan(pl));
   CF_TRY(check_ptr(fhat, "fhat"));
   CF_TRY(check_ptr(phat, "phat"));
+  CF_TRY(check_disjoint(phat, spec_bytes(pl), fhat, spec_bytes(pl), true, "phat must be fhat itself or not overlap it"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->mixed())
     return solve_t<float>(pl, static_cast<const cx<float>*>(fhat), static_cast<cx<float>*>(phat), s);
@@ -1272,6 +1287,7 @@ cf_status cf_solve_spectral_slabs(cf_plan* pl, int n_slabs, const void* fhat, vo
   CF_TRY(check_plan(pl));
   CF_TRY(check_ptr(fhat, "fhat"));
   CF_TRY(check_ptr(phat, "phat"));
+  CF_TRY(check_disjoint(phat, spec_bytes(pl), fhat, spec_bytes(pl), true, "phat must be fhat itself or not overlap it"));
   CF_TRY(check_ptr(iface, "iface"));
   if (pl->opt.flags & CF_PLAN_Y_DCT) return fail(CF_ERR_ARG, "the y-transform solve has no partitions");
   if (n_slabs < 1 || pl->P % n_slabs != 0)
@@ -1286,6 +1302,7 @@ cf_status cf_solve_spectral_slabs_noalloc(cf_plan* pl, int n_slabs, const void* 
   CF_TRY(check_plan(pl));
   CF_TRY(check_ptr(fhat, "fhat"));
   CF_TRY(check_ptr(phat, "phat"));
+  CF_TRY(check_disjoint(phat, spec_bytes(pl), fhat, spec_bytes(pl), true, "phat must be fhat itself or not overlap it"));
   if (pl->opt.flags & CF_PLAN_Y_DCT) return fail(CF_ERR_ARG, "the y-transform solve has no partitions");
   if (n_slabs < 1 || pl->P % n_slabs != 0)
     return fail(CF_ERR_ARG, "n_slabs must divide the plan's partition count " + std::to_string(pl->P));
@@ -1331,6 +1348,9 @@ cf_status cf_divergence(cf_plan* pl, const double* u, const double* v, const dou
   CF_TRY(check_ptr(w, "w"));
   CF_TRY(check_ptr(f, "f"));
   if (!std::isfinite(scale)) return fail(CF_ERR_ARG, "scale must be finite");
+  for (const double* q : {u, v, w})
+    CF_TRY(check_disjoint(f, field_bytes(pl, sizeof(double)), q, field_bytes(pl, sizeof(double)), false,
+                          "f must not overlap u, v or w"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   return timed(pl, CF_K_DIVERGENCE, s, "divergence launch", [&] {
     return cf::launch_divergence(u, v, w, f, pl->d_rdy, 1.0 / pl->dx, 1.0 / pl->dz, scale, pl->nx, pl->ny,
@@ -1398,6 +1418,10 @@ cf_status cf_plane_stats(cf_plan* pl, const void* u, const void* v, const void* 
   const void* ptrs[4] = {u, v, w, stats};
   const char* names[4] = {"u", "v", "w", "stats"};
   for (int q = 0; q < 4; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  const size_t es = pl->mixed() ? sizeof(float) : sizeof(double);
+  for (int q = 0; q < 3; ++q)
+    CF_TRY(check_disjoint(stats, (size_t)pl->ny * 6 * sizeof(double), ptrs[q], field_bytes(pl, es), false,
+                          "stats must not overlap u, v or w"));
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = pl->mixed() ? cf::launch_plane_stats<float>(static_cast<const float*>(u), static_cast<const float*>(v),
                                                              static_cast<const float*>(w), stats, pl->g32, 0, s)
@@ -1580,6 +1604,14 @@ cf_status cf_rhs_adjoint(cf_plan* pl, const void* u, const void* v, const void* 
   const void* ptrs[9] = {u, v, w, lu, lv, lw, gu, gv, gw};
   const char* names[9] = {"u", "v", "w", "lu", "lv", "lw", "gu", "gv", "gw"};
   for (int q = 0; q < 9; ++q) CF_TRY(check_ptr(ptrs[q], names[q]));
+  {
+    // the stencil reads neighbours of every output cell: outputs disjoint from
+    // the inputs and from each other
+    const size_t nb = field_bytes(pl, pl->mixed() ? sizeof(float) : sizeof(double));
+    for (int o = 6; o < 9; ++o)
+      for (int q = 0; q < 9; ++q)
+        if (q != o) CF_TRY(check_disjoint(ptrs[o], nb, ptrs[q], nb, false, "gu, gv, gw must not overlap each other or the inputs"));
+  }
   if (!(nu >= 0.0) || !std::isfinite(nu)) return fail(CF_ERR_ARG, "nu must be finite and >= 0");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (pl->mixed())

@@ -228,6 +228,28 @@ def test_bad_tensor_arguments_rejected():
         pl.poisson_solve(f.transpose(1, 2).contiguous().transpose(1, 2))
 
 
+def test_overlapping_outputs_of_other_entry_points_rejected():
+    """The divergence's output inside a velocity array, a spectral solve's
+    output overlapping its input at another offset, and plane statistics
+    written into the field they average are refused (CF_ERR_ARG)."""
+    from paper_2104_08863_amd._lib import ChanflowError
+    nx, ny, nz = 32, 16, 8
+    pl, box = plan_for(nx, ny, nz, 2.0)
+    u, v, w = (torch.tensor(q, device=dev()) for q in synth.uniform_velocity(nx, ny, nz, seed=1))
+    with pytest.raises(ChanflowError):
+        pl.divergence(u, v, w, out=v)
+    fh = pl.forward_spectral(pl.divergence(u, v, w))
+    n = fh.numel()
+    buf = torch.zeros(2 * n, dtype=fh.dtype, device=dev())
+    buf[:n].copy_(fh.reshape(-1))
+    a = buf[:n].view(fh.shape)
+    with pytest.raises(ChanflowError):
+        pl.solve_spectral(a, out=buf[1:n + 1].view(fh.shape))
+    assert torch.equal(pl.solve_spectral(a, out=a), pl.solve_spectral(fh))   # in place is fine
+    with pytest.raises(ChanflowError):
+        pl.plane_stats(u, v, w, out=u.view(-1)[:ny * 6].view(ny, 6))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_partially_overlapping_output_rejected(precision):
     """p may be f itself, but an output that overlaps f at another offset is
