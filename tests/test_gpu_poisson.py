@@ -189,6 +189,32 @@ def test_poisson_solve_matches_oracle(nx, ny, nz, gamma, parts):
     assert np.array_equal(pg2, pg)
 
 
+@pytest.mark.parametrize("ny,precision", [(1024, "fp64"), (1023, "fp64"), (2048, "mixed"), (2047, "mixed")])
+def test_largest_wall_normal_sizes(ny, precision):
+    """The largest ny each precision takes (64 partitions of 16 rows in FP64,
+    of 32 in mixed precision), and one row fewer (the last partition padded),
+    on a thin x-z grid: the Poisson solve against the oracle.  The bounds grow
+    with ny because the conditioning of the lowest wall-normal modes does: in
+    FP64 5e-12 instead of the 1e-12 of ny <= 256 (per line, two correct FP64
+    solvers differ by about 2e-11 at ny = 1024 and k^2 = 0.25; measured field
+    rel-L2 1.9e-12); in mixed precision one refinement pass reaches 1.3e-6 at
+    ny = 2048 (bound 3e-6) and a second pass brings it below 1e-6."""
+    nx, nz = 8, 6
+    mk = lambda **kw: plan_for(nx, ny, nz, 2.0, precision=precision, **kw)  # noqa: E731
+    pl, box = mk()
+    info = pl.info()
+    assert info["n_parts"] == 64 and info["rows_per_part"] == (16 if precision == "fp64" else 32)
+    f = synth.uniform_rhs(nx, ny, nz, seed=7)
+    ref = O.poisson(torch.tensor(f), box).numpy()
+    e1 = rel(pl.poisson_solve(torch.tensor(f, device=dev())).cpu().numpy(), ref)
+    if precision == "fp64":
+        assert e1 <= 5e-12
+    else:
+        e2 = rel(mk(refine_passes=2)[0].poisson_solve(torch.tensor(f, device=dev())).cpu().numpy(), ref)
+        print(f"mixed ny={ny}: rel-L2 one pass {e1:.3e}, two passes {e2:.3e}")
+        assert e1 <= 3e-6 and e2 <= 1e-6 and e2 < e1
+
+
 def test_poisson_64cubed_config_and_determinism():
     wl = synth.WORKLOADS["poisson64"]
     pl, box = plan_for(wl.nx, wl.ny, wl.nz, wl.gamma, lx=wl.lx, lz=wl.lz)
