@@ -67,8 +67,8 @@ typedef struct {
   int fp64_kx;        /* CF_MIXED: lines with kx < fp64_kx and min(kz, nz-kz) < fp64_kz */
   int fp64_kz;        /*   are solved in FP64 (default 4, 4) */
   int refine_passes;  /* CF_MIXED: FP64 residual + correction solves (default 1; one pass
-                         reaches about 1e-6 relative up to ny ~ 1024, two passes are
-                         needed beyond: 1.3e-6 and 8.5e-9 at ny = 2048) */
+                         reaches <= 1e-6 relative on grids up to ny = 768 as tested, at
+                         the largest ny two are needed: 1.3e-6 and 8.5e-9 at ny = 2048) */
   int flags;          /* CF_PLAN_STEP: allocate the projection-step workspace;
                          CF_PLAN_ADJOINT: also the workspace of its adjoint;
                          CF_PLAN_Y_DCT, CF_PLAN_TUNE_PARTS: see below */
