@@ -21,6 +21,9 @@ CASES = [
     (96, 136, 24, 2.5, 1e-3, 1 / 550),
     # ny = 130: 11 partitions of 12 rows, the last one padded by two
     (64, 130, 32, 2.5, 1e-3, 1 / 550),
+    # the largest FP64 ny less one: 64 partitions of 16 rows (one padded), a
+    # ragged last y-chunk of the fused RK2 pass, partial x tiles
+    (16, 1023, 8, 2.0, 1e-4, 1 / 550),
 ]
 
 
@@ -47,13 +50,16 @@ def test_projection_step_matches_oracle(nx, ny, nz, gamma, dt, nu):
     p = torch.empty_like(ug)
     u1, v1, w1 = pl.projection_step(ug, vg, wg, dt, nu, fx, p=p)
     ref = O.projection_step(*(torch.tensor(q) for q in (u, v, w)), box, dt, nu, fx, return_pressure=True)
+    # the lowest wall-normal modes' conditioning grows with ny: two correct FP64
+    # solvers differ more on tall grids (v through dp/dy: 4.3e-12 at ny = 1023)
+    tol = 1e-12 if ny <= 256 else 1e-11
     for got, want, name in zip((u1, v1, w1, p), ref, ("u", "v", "w", "p")):
         e = rel(got.cpu().numpy(), want.numpy())
-        assert e <= 1e-12, f"{name}: rel-L2 {e:.3e}"
+        assert e <= tol, f"{name}: rel-L2 {e:.3e}"
     assert torch.all(v1[-1] == 0)
     d = O.divergence(u1.cpu(), v1.cpu(), w1.cpu(), box)
     d0 = O.divergence(*(torch.tensor(q) for q in (u, v, w)), box)
-    assert d.abs().max() <= 1e-12 * d0.abs().max()
+    assert d.abs().max() <= tol * d0.abs().max()
 
 
 def test_projection_step_in_place_and_repeatable():
