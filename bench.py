@@ -161,6 +161,26 @@ def pmc_record(base, name, workload, units, exclude=()):
                       f"write_factor: {kib / cw[(copy, 'WRITE_SIZE')]:.3f}"])
 
 
+def summarize_counters(base, kernel):
+    """Mean per dispatch of every counter in the rocprofv3 --pmc passes under
+    `base` (each subdirectory holding a run_counter_collection.csv) for the
+    kernels whose name contains `kernel`, as a markdown table."""
+    import collections
+    import csv
+    import glob
+    import re
+    agg = collections.defaultdict(list)
+    for path in sorted(glob.glob(os.path.join(base, "*", "run_counter_collection.csv"))):
+        for r in csv.DictReader(open(path)):
+            k = re.sub(r"\(.*", "", r["Kernel_Name"]).replace("void ", "")
+            if kernel in k:
+                agg[(k, r["Counter_Name"])].append(float(r["Counter_Value"]))
+    out = ["| kernel | counter | dispatches | mean per dispatch |", "|---|---|---:|---:|"]
+    for (k, c), v in sorted(agg.items()):
+        out.append(f"| `{k}` | {c} | {len(v)} | {sum(v) / len(v):.4g} |")
+    return "\n".join(out)
+
+
 def summarize_trace(path):
     """Markdown table of a rocprofv3 --stats kernel_stats.csv."""
     import csv
@@ -759,6 +779,9 @@ def main():
     ap.add_argument("--pmc-record", nargs=4, metavar=("DIR", "NAME", "WORKLOAD", "UNITS"),
                     help="print the traffic record of a whole path (step_fp64, poisson_mixed) from the counter "
                          "passes under DIR, per one of the UNITS steps or solves the profiled run made, and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("DIR", "KERNEL"),
+                    help="print the mean per dispatch of every counter of the --pmc passes under DIR for the "
+                         "kernels whose name contains KERNEL, and exit")
     ap.add_argument("--pmc-exclude", nargs="*", default=[], metavar="NAME",
                     help="with --pmc-record: kernels (name substrings) to leave out, e.g. input generation")
     ap.add_argument("--trace-last", type=int, default=0, metavar="N",
@@ -780,6 +803,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
+        return
+    if args.summarize_counters:
+        print(summarize_counters(*args.summarize_counters))
         return
     if args.pmc_record:
         d, name, workload, units = args.pmc_record

@@ -91,3 +91,13 @@ def test_model_bytes_of_the_mixed_solve():
     x, zyz = 8 + 4, 3 * (4 + 4)
     first_out, resid, accum = 4 + 4, 4 + 8 + 4, 4 + 4 + 8
     assert bench.MODEL_BYTES_PER_POINT["poisson_mixed_refine1"] == x + zyz + first_out + resid + zyz + accum
+
+
+def test_summarize_counters_means_per_kernel_and_counter(tmp_path):
+    base = str(tmp_path)
+    a, b = "void cf::k_a<double, 64>(int)", "void cf::k_b(int)"
+    _counters(f"{base}/p1", [(a, "SQ_INSTS_VALU", 10), (a, "SQ_INSTS_VALU", 30), (b, "SQ_INSTS_VALU", 7)])
+    _counters(f"{base}/p2", [(a, "GRBM_GUI_ACTIVE", 8), (a, "GRBM_GUI_ACTIVE", 16)])
+    rows = [l for l in bench.summarize_counters(base, "k_a").splitlines() if l.startswith("| `")]
+    assert rows == ["| `cf::k_a<double, 64>` | GRBM_GUI_ACTIVE | 2 | 12 |",
+                    "| `cf::k_a<double, 64>` | SQ_INSTS_VALU | 2 | 20 |"]
