@@ -75,6 +75,7 @@ HOST_SIGNATURES = {
     "cfh_irfft": (_I, [_I, _I, _P, _P]),
     "cfh_pdd_line": (_I, [_I, _I, _P, _P, _D, _I, _I, _P, _P]),
     "cfh_pdd_line_grouped": (_I, [_I, _I, _I, _P, _P, _D, _I, _P, _P]),
+    "cfh_xcd_slab_block": (_I, [_I, _I]),
 }
 
 _lib = None

@@ -65,6 +65,19 @@ CF_HD float rcp(float x) {
 template <typename T> CF_HD T cf_max(T a, T b) { return a > b ? a : b; }
 template <typename T> CF_HD T cf_min(T a, T b) { return a < b ? a : b; }
 
+// Work order for the 8 XCDs, each with its own L2.  The hardware deals
+// blocks round-robin (block b to XCD b mod 8); for a grid made of groups of n
+// consecutive work items (n a multiple of 8), block b is given the item that
+// puts XCD x on the contiguous run [x n/8, (x+1) n/8) of every group, so items
+// beside each other, which read each other's edge cells, do so from one L2.
+// With n the whole grid each XCD gets one run.  A permutation of the grid
+// either way (identity when n is not a multiple of 8).
+CF_HD int xcd_slab_block(int b, int n) {
+  if (n & 7) return b;
+  const int x = b & 7, s = b >> 3, per = n >> 3;
+  return (s / per) * n + x * per + s % per;
+}
+
 // Modes of the partitioned solve.  kWhole: every partition of a line in one
 // block.  The two slab modes split the same computation at the point where a
 // partition needs data from the others (the paper's exchange across

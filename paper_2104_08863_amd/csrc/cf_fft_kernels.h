@@ -322,18 +322,6 @@ struct SrcResidual {
   }
 };
 
-// Row block of a forward x transform: block index b of ny * nzb blocks (nzb
-// blocks of K rows per y-plane).  Blocks are dealt round-robin to the 8 XCDs;
-// when nzb is a multiple of 8, XCD x takes the contiguous blocks
-// [x nzb/8, (x+1) nzb/8) of every plane, so the z-neighbour rows that the
-// divergence and residual sources read across block edges are mostly in the
-// same L2 (the mixed 2048x512x1536 solve's residual transform: 9.8 -> 8.7 ms).
-__device__ __forceinline__ int xcd_slab_block(int b, int nzb) {
-  if (nzb & 7) return b;
-  const int x = b & 7, s = b >> 3, per = nzb >> 3;
-  return (s / per) * nzb + x * per + s % per;
-}
-
 template <typename T, int NH, typename Src>
 __global__ void __launch_bounds__((XCfg<T, NH>::THREADS))
 k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* tw, const cx<T>* twp, int ny, int nz) {
@@ -346,6 +334,10 @@ k_r2c_x(Src src, cx<T>* __restrict__ spec, const cx<T>* tw, const cx<T>* twp, in
   __shared__ cx<T> stw[NTW], stwp[NTW];
   XTw<T, NH>::stage(stw, stwp, tw, twp);
   if constexpr (XCfg<T, NH>::kLdsTw) __syncthreads();
+  // ny * nzb row blocks (nzb blocks of K rows per y-plane), each XCD on a
+  // contiguous run of every plane's blocks: the z-neighbour rows that the
+  // divergence and residual sources read across block edges are mostly in the
+  // same L2 (the mixed 2048x512x1536 solve's residual transform: 9.8 -> 8.7 ms)
   const int nzb = (nz + K - 1) / K;
   const int lb = xcd_slab_block(blockIdx.x, nzb);
   const int j = lb / nzb;

@@ -294,4 +294,9 @@ int cfh_pdd_line_grouped(int ny, int P, int G, const double* a, const double* c,
   return fp32 ? pdd_line_grouped<float>(ny, P, G, a, c, k2, d, x) : pdd_line_grouped<double>(ny, P, G, a, c, k2, d, x);
 }
 
+// The work item that block b of a launch takes (groups of n items, each XCD
+// on a contiguous run of every group): the index map of the row-block and
+// stencil-tile launches.
+int cfh_xcd_slab_block(int b, int n) { return cf::xcd_slab_block(b, n); }
+
 }

@@ -102,9 +102,9 @@ struct RkFusedTile {
 
 // At least four waves per SIMD: the register cap this sets (128 VGPRs, some
 // spilled in FP64) costs less than the latency hiding fewer waves would lose.
-// Blocks are dealt round-robin to the 8 XCDs; the tile index is remapped so
-// that each XCD walks a contiguous run of tiles and neighbouring tiles share
-// the halo lines in one L2.
+// The tile index is remapped (xcd_slab_block over the whole grid) so that each
+// XCD walks one contiguous run of tiles and neighbouring tiles share the halo
+// lines in one L2 (runs within each y-chunk instead: within 1.5 %, either way).
 template <typename T, int TX, int TZ, int CY>
 __global__ void __launch_bounds__(TX * TZ, 4)
 k_rk2_fused(const T* __restrict__ u, const T* __restrict__ v, const T* __restrict__ w, T* uo, T* vo, T* wo,
@@ -117,11 +117,7 @@ k_rk2_fused(const T* __restrict__ u, const T* __restrict__ v, const T* __restric
   __shared__ T sy[4 * (CY + 4)];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int ntx = (nx + TX - 1) / TX, ntz = (nz + TZ - 1) / TZ;
-  int b = blockIdx.x;
-  {
-    const int nb = gridDim.x;
-    if ((nb & 7) == 0) b = (b & 7) * (nb >> 3) + (b >> 3);
-  }
+  int b = xcd_slab_block(blockIdx.x, gridDim.x);
   const int bx = b % ntx;
   b /= ntx;
   const int bz = b % ntz;

@@ -170,3 +170,21 @@ def test_grouped_drop_matches_oracle_pdd_of_the_groups(H, ny, Pn, G):
         th = O.thomas(torch.tensor(a), b[:, 0], torch.tensor(c), torch.tensor(d)).numpy()
         if delta < 1e-15:
             assert np.abs(got - th).max() <= 1e-11 * np.abs(th).max(), k2
+
+
+@pytest.mark.parametrize("n,groups", [(8, 1), (64, 3), (2048, 8), (8192, 2), (24, 5), (12, 4), (7, 3)])
+def test_xcd_work_order_is_a_permutation_in_runs(H, n, groups):
+    """The block -> work item map of the row-block and stencil-tile launches:
+    a permutation of the grid; for n a multiple of 8 the blocks one XCD
+    receives (b mod 8 = x) take, in launch order, the contiguous run
+    [x n/8, (x+1) n/8) of each group of n items in turn; otherwise the identity."""
+    nb = n * groups
+    got = [H.cfh_xcd_slab_block(b, n) for b in range(nb)]
+    assert sorted(got) == list(range(nb))
+    if n % 8:
+        assert got == list(range(nb))
+        return
+    per = n // 8
+    for x in range(8):
+        items = got[x::8]
+        assert items == [g * n + x * per + s for g in range(groups) for s in range(per)]
