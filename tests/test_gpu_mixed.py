@@ -54,6 +54,26 @@ def test_mixed_poisson_refinement(nx, ny, nz, gamma):
         assert errs[2] < errs[1]
 
 
+def test_mixed_long_partitions_default_block():
+    """ny = 768 (the mixed forward + adjoint workload's wall-normal size) takes
+    P = 32 partitions of 24 rows, a length only the FP32 solve compiles, and by
+    default 16 lines per block (512 threads); one refinement meets the oracle
+    at the bar of the other sizes."""
+    nx, ny, nz = 32, 768, 16
+    yf, box, mk = plans(nx, ny, nz, 2.5, 4 * np.pi, 2 * np.pi)
+    pl = mk(1)
+    info = pl.info()
+    assert (info["n_parts"], info["rows_per_part"], info["lines_per_block"]) == (32, 24, 16)
+    u, v, w = synth.powerlaw_velocity(nx, ny, nz, seed=1)
+    f = O.divergence(*(torch.tensor(q) for q in (u, v, w)), box)
+    f = f - O.mean_w(f, box)
+    ref = O.poisson(f, box).numpy()
+    p = pl.poisson_solve(torch.tensor(f.numpy(), device=dev())).cpu().numpy()
+    e = rel(p, ref)
+    print(f"mixed {nx}x{ny}x{nz} (P = 32 x 24 rows): rel-L2 {e:.3e}")
+    assert e <= 1e-6
+
+
 def test_mixed_poisson_alias_and_fp64_lines():
     nx, ny, nz = 64, 32, 48
     yf, box, mk = plans(nx, ny, nz, 2.0, 2 * np.pi, np.pi)
