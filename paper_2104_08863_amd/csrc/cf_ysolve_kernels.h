@@ -70,10 +70,11 @@ __host__ __device__ constexpr size_t ysolve_lds_bytes(int nyp, int P, int LB, bo
 // The FP32 24-row instance is held to 128 VGPRs (four waves per SIMD, two
 // 512-thread blocks per CU; the dropped form then spills 16 registers): 5 %
 // faster on 2048x768x2048 than at its natural 153 VGPRs and one block per CU.
-// The 32-row instance spills 46 at that cap and is 20 % slower, so it keeps its
-// registers.
+// The 32-row instance spills 46 at that cap and is 20 % slower; held to 168
+// (three waves per SIMD, one register spilled) instead of its natural 169 it
+// is 2-3 % faster on 2048x512x1536.
 template <typename T, int M, int MODE, bool DROP>
-__global__ void __launch_bounds__(512, (sizeof(T) == 4 && M == 24) ? 4 : 1)
+__global__ void __launch_bounds__(512, sizeof(T) != 4 ? 1 : M == 24 ? 4 : M == 32 ? 3 : 1)
 k_ysolve(const cx<T>* fin, cx<T>* pout, const T* __restrict__ acoef,
          const T* __restrict__ ccoef, const T* __restrict__ kx2, const T* __restrict__ kz2,
          const int* __restrict__ blist, YArgs ya) {

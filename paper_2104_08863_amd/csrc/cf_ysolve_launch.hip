@@ -22,15 +22,18 @@ bool ysolve_m_compiled(int m, bool fp64) {
   }
 }
 
-// Default lines per block: about 256 threads per block with 8 to 16 lines, or
-// 512 threads with 8 to 32 lines for the FP32-only partitions of more than 16
-// rows, and at least one wave.  Measured on MI355X for the default
-// partitionings of the workload grids this is the fastest block or within 2 %
-// of it (P = 32 partitions of 24 rows on 2048x768x2048: 7.0 ms per launch at
-// 16 lines against 7.4 at 8); other shapes can be chosen by measurement.
+// Default lines per block: about 256 threads per block with 8 to 16 lines (to
+// 32 for the FP32-only partitions of more than 16 rows), and at least one
+// wave.  Those FP32 partitions take at least 16 lines, so that each row of a
+// block is a 128-byte run of consecutive lines, up to 512 threads.  Measured
+// on MI355X for the default partitionings of the workload grids this is the
+// fastest block or within 2 % of it (P = 32 partitions of 24 rows on
+// 2048x768x2048: 7.0 ms per launch at 16 lines against 7.4 at 8); other shapes
+// can be chosen by measurement.
 int ysolve_default_lb(int P, int M) {
   const int hi = M > 16 ? 32 : 16;
-  int lb = (M > 16 ? 512 : 256) / P;
+  int lb = 256 / P;
+  if (M > 16 && lb < 16) lb = 16 * P <= 512 ? 16 : 512 / P;
   lb = lb < 8 ? 8 : (lb > hi ? hi : lb);
   if (lb * P < 64) lb = (64 + P - 1) / P;
   return lb;
