@@ -43,7 +43,11 @@ def test_rhs_adjoint_matches_autograd(nx, ny, nz, gamma):
 
 @pytest.mark.parametrize("nx,ny,nz,gamma,dt,nu", [(32, 16, 24, 2.0, 1e-3, 1 / 550),
                                                    (24, 12, 12, 2.5, 5e-3, 1 / 50),
-                                                   (64, 32, 48, 2.0, 1e-3, 1 / 550)])
+                                                   (64, 32, 48, 2.0, 1e-3, 1 / 550),
+                                                   # tiles per y-chunk a multiple of 8 for the stage
+                                                   # recompute and the transposed stencil (their
+                                                   # XCD-run tile order), two 32-plane chunks
+                                                   (128, 40, 32, 2.0, 1e-3, 1 / 550)])
 def test_step_adjoint_matches_oracle_gradient(nx, ny, nz, gamma, dt, nu):
     pl, box = setup(nx, ny, nz, gamma)
     fx = 3 * nu
