@@ -343,7 +343,7 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
 
 // g* = g - W G phi (weighted correction of the projection transpose);
 // W = dy_j for u and w, dyc_j for v (so the v part is g - (phi_{j+1} - phi_j)).
-template <typename T>
+template <typename T, bool NT>
 __global__ void __launch_bounds__(256)
 k_correct_w(const T* __restrict__ gu, const T* __restrict__ gv, const T* __restrict__ gw, T* ou, T* ov, T* ow,
             const double* __restrict__ phi, AdjGeo<T> G) {
@@ -359,9 +359,10 @@ k_correct_w(const T* __restrict__ gu, const T* __restrict__ gv, const T* __restr
   const int kp = (k + 1 == g.nz) ? 0 : k + 1;
   const double p0 = phi[id];
   const T dyj = G.dy[j];
-  ou[id] = gu[id] - dyj * (T(phi[jk * g.nx + ip] - p0) * g.rdx);
-  ow[id] = gw[id] - dyj * (T(phi[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz);
-  ov[id] = (j == g.ny - 1) ? T(0) : gv[id] - T(phi[id + (long)g.nz * g.nx] - p0);
+  // g and g* are touched once (streamed when NT, as in the forward correction)
+  st_once<NT>(ld_once<NT>(&gu[id]) - dyj * (T(phi[jk * g.nx + ip] - p0) * g.rdx), &ou[id]);
+  st_once<NT>(ld_once<NT>(&gw[id]) - dyj * (T(phi[((long)j * g.nz + kp) * g.nx + i] - p0) * g.rdz), &ow[id]);
+  st_once<NT>((j == g.ny - 1) ? T(0) : ld_once<NT>(&gv[id]) - T(phi[id + (long)g.nz * g.nx] - p0), &ov[id]);
 }
 
 }  // namespace cf

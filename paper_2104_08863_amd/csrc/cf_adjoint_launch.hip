@@ -46,7 +46,10 @@ hipError_t launch_correct_w(const T* gu, const T* gv, const T* gw, T* ou, T* ov,
   const long n = (long)g.g.nx * g.g.ny * g.g.nz;
   const int th = 256;
   const long blocks = (n + th - 1) / th;
-  hipLaunchKernelGGL((k_correct_w<T>), dim3(blocks), dim3(th), 0, st, gu, gv, gw, ou, ov, ow, phi, g);
+  if (n * (long)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_correct_w<T, true>), dim3(blocks), dim3(th), 0, st, gu, gv, gw, ou, ov, ow, phi, g);
+  else
+    hipLaunchKernelGGL((k_correct_w<T, false>), dim3(blocks), dim3(th), 0, st, gu, gv, gw, ou, ov, ow, phi, g);
   return hipGetLastError();
 }
 

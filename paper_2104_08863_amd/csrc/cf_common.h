@@ -65,6 +65,26 @@ CF_HD float rcp(float x) {
 template <typename T> CF_HD T cf_max(T a, T b) { return a > b ? a : b; }
 template <typename T> CF_HD T cf_min(T a, T b) { return a < b ? a : b; }
 
+// A load and a store of a value that a kernel touches once: non-temporal when
+// NT (streamed past the caches; the launches choose it for fields larger than
+// the XCDs' L2s together), plain otherwise.
+#if defined(__HIPCC__)
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_once(const T* a) {
+  if constexpr (NT) return __builtin_nontemporal_load(a);
+  else return *a;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_once(T v, T* a) {
+  if constexpr (NT) __builtin_nontemporal_store(v, a);
+  else *a = v;
+}
+#endif
+// Field size from which the streaming corrections take non-temporal loads and
+// stores: the 8 XCDs' L2s together (32 MiB); smaller fields stay cached for
+// the next kernel (the 64^3 time loop is 2-4 % slower with them streamed).
+constexpr long kStreamBytes = 32L << 20;
+
 // Work order for the 8 XCDs, each with its own L2.  The hardware deals
 // blocks round-robin (block b to XCD b mod 8); for a grid made of groups of n
 // consecutive work items (n a multiple of 8), block b is given the item that

@@ -64,7 +64,10 @@ hipError_t launch_correct(T* u, T* v, T* w, const double* p, const Geo<T>& g, T 
   const long n = (long)g.nx * g.ny * g.nz;
   const int th = 256;
   const long blocks = (n + th - 1) / th;
-  hipLaunchKernelGGL((k_correct<T>), dim3(blocks), dim3(th), 0, s, u, v, w, p, g, dt);
+  if (n * (long)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_correct<T, true>), dim3(blocks), dim3(th), 0, s, u, v, w, p, g, dt);
+  else
+    hipLaunchKernelGGL((k_correct<T, false>), dim3(blocks), dim3(th), 0, s, u, v, w, p, g, dt);
   return hipGetLastError();
 }
 
@@ -93,8 +96,12 @@ int correct_stats_chunks(int nx, int ny, int nz) {
 template <typename T>
 hipError_t launch_correct_stats(T* u, T* v, T* w, const double* p, const Geo<T>& g, T dt, double* part, int nch,
                                 double* st, int accumulate, hipStream_t s) {
-  hipLaunchKernelGGL((k_correct_stats<T, 256>), dim3((long)g.ny * nch), dim3(256), 0, s, u, v, w, p, g, dt, part,
-                     nch);
+  if ((long)g.nx * g.ny * g.nz * (long)sizeof(T) >= kStreamBytes)
+    hipLaunchKernelGGL((k_correct_stats<T, 256, true>), dim3((long)g.ny * nch), dim3(256), 0, s, u, v, w, p, g, dt,
+                       part, nch);
+  else
+    hipLaunchKernelGGL((k_correct_stats<T, 256, false>), dim3((long)g.ny * nch), dim3(256), 0, s, u, v, w, p, g, dt,
+                       part, nch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int n = g.ny * 6;
