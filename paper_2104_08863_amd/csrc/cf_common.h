@@ -79,10 +79,31 @@ __device__ __forceinline__ void st_once(T v, T* a) {
   if constexpr (NT) __builtin_nontemporal_store(v, a);
   else *a = v;
 }
+template <bool NT, typename T>
+__device__ __forceinline__ cx<T> ld_once(const cx<T>* a) {
+  if constexpr (NT) {
+    const T* p = reinterpret_cast<const T*>(a);
+    return mk(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1));
+  } else {
+    return *a;
+  }
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_once(cx<T> v, cx<T>* a) {
+  if constexpr (NT) {
+    T* p = reinterpret_cast<T*>(a);
+    __builtin_nontemporal_store(v.re, p);
+    __builtin_nontemporal_store(v.im, p + 1);
+  } else {
+    *a = v;
+  }
+}
 #endif
-// Field size from which the streaming corrections take non-temporal loads and
-// stores: the 8 XCDs' L2s together (32 MiB); smaller fields stay cached for
-// the next kernel (the 64^3 time loop is 2-4 % slower with them streamed).
+// Data size from which the kernels that touch their arrays once (the
+// corrections, the z transforms, the wall-normal solve, the fused RK2 pass's
+// output) take non-temporal loads and stores: the 8 XCDs' L2s together
+// (32 MiB).  Smaller arrays stay cached for the next kernel (streamed, the
+// 64^3 time loop was 2-4 % slower).
 constexpr long kStreamBytes = 32L << 20;
 
 // Work order for the 8 XCDs, each with its own L2.  The hardware deals

@@ -92,7 +92,9 @@ struct ZCfg {
   static constexpr int THREADS = LPB * FftT<N>::TPL;
 };
 
-template <typename T, int N, bool INV>
+// NT: lines read and written once, streamed (non-temporal) for large spectra:
+// the FP64 512-point transforms on 1024x256x512 take 380 instead of 411-434 us.
+template <typename T, int N, bool INV, bool NT>
 __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __restrict__ tw, int no,
         int ni) {
@@ -112,7 +114,7 @@ k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __r
   for (int q = 0; q < F::E / F::R0; ++q) {
     const int b = tl + q * F::TPL;
 #pragma unroll
-    for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? g[st_in(N, F::R0, b, r)] : mk(T(0), T(0));
+    for (int r = 0; r < F::R0; ++r) x[q * F::R0 + r] = ok ? ld_once<NT>(&g[st_in(N, F::R0, b, r)]) : mk(T(0), T(0));
   }
   fft_passes<N, INV, T, 0>(x, tl, lds + lb * lpad_len(N), tw);
   if (ok) {
@@ -120,7 +122,7 @@ k_fft_z(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const cx<T>* __r
     for (int q = 0; q < F::E / F::RL; ++q) {
       const int b = tl + q * F::TPL;
 #pragma unroll
-      for (int r = 0; r < F::RL; ++r) o[b + r * (N / F::RL)] = x[q * F::RL + r];
+      for (int r = 0; r < F::RL; ++r) st_once<NT>(x[q * F::RL + r], &o[b + r * (N / F::RL)]);
     }
   }
 }

@@ -25,10 +25,15 @@ static hipError_t fft_z_n(bool inv, const cx<T>* src, cx<T>* dst, const cx<T>* t
   using C = ZCfg<T, N>;
   const long blocks = ((long)no * ni + C::LPB - 1) / C::LPB;
   if (blocks <= 0) return hipSuccess;
-  if (inv)
-    hipLaunchKernelGGL((k_fft_z<T, N, true>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
+  const bool nt = (long)no * ni * N * (long)sizeof(cx<T>) >= kStreamBytes;
+  if (inv && nt)
+    hipLaunchKernelGGL((k_fft_z<T, N, true, true>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
+  else if (inv)
+    hipLaunchKernelGGL((k_fft_z<T, N, true, false>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
+  else if (nt)
+    hipLaunchKernelGGL((k_fft_z<T, N, false, true>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
   else
-    hipLaunchKernelGGL((k_fft_z<T, N, false>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
+    hipLaunchKernelGGL((k_fft_z<T, N, false, false>), dim3(blocks), dim3(C::THREADS), 0, s, src, dst, tw, no, ni);
   return hipGetLastError();
 }
 

@@ -47,15 +47,21 @@ hipError_t launch_rk2_fused(const T* u, const T* v, const T* w, T* uo, T* vo, T*
   const long cols = (long)((g.nx + RKF_TX - 1) / RKF_TX) * ((g.nz + RKF_TZ - 1) / RKF_TZ);
   auto blocks = [&](int cy) { return cols * ((g.ny + cy - 1) / cy); };
   const dim3 th(RKF_TX * RKF_TZ);
-  if (blocks(128) >= 512)
-    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 128>), dim3(blocks(128)), th, 0, s, u, v, w, uo, vo, wo, g,
-                       dt, nu, fx);
-  else if (blocks(32) >= 512)
-    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 32>), dim3(blocks(32)), th, 0, s, u, v, w, uo, vo, wo, g, dt,
-                       nu, fx);
-  else
-    hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, 8>), dim3(blocks(8)), th, 0, s, u, v, w, uo, vo, wo, g, dt,
-                       nu, fx);
+  const bool nt = (long)g.nx * g.ny * g.nz * (long)sizeof(T) >= kStreamBytes;
+#define CF_RKF_GO(CY, NT)                                                                                          \
+  hipLaunchKernelGGL((k_rk2_fused<T, RKF_TX, RKF_TZ, CY, NT>), dim3(blocks(CY)), th, 0, s, u, v, w, uo, vo, wo, g, \
+                     dt, nu, fx)
+  if (blocks(128) >= 512) {
+    if (nt) CF_RKF_GO(128, true);
+    else CF_RKF_GO(128, false);
+  } else if (blocks(32) >= 512) {
+    if (nt) CF_RKF_GO(32, true);
+    else CF_RKF_GO(32, false);
+  } else {
+    if (nt) CF_RKF_GO(8, true);
+    else CF_RKF_GO(8, false);
+  }
+#undef CF_RKF_GO
   return hipGetLastError();
 }
 

@@ -45,8 +45,17 @@ static hipError_t ysolve_go(long blocks, const int* blist, const YArgs& ya, int 
   if (blocks <= 0) return hipSuccess;
   const int nyp = ya.P * M;  // rows of the partitions (padded past ny)
   const size_t lds = MODE == kSlabLocal ? sizeof(T) * 2 * (size_t)nyp : ysolve_lds_bytes<T>(nyp, ya.P, ya.LB, DROP);
-  hipLaunchKernelGGL((k_ysolve<T, M, MODE, DROP>), dim3(blocks), dim3(threads), lds, s, fin, pout, a, c, kx2, kz2,
-                     blist, ya);
+  if constexpr (MODE == kWhole) {
+    // the slab passes read their right-hand side twice: only the one-pass
+    // solve streams it
+    if ((long)ya.nlines * ya.ny * (long)sizeof(cx<T>) >= kStreamBytes) {
+      hipLaunchKernelGGL((k_ysolve<T, M, MODE, DROP, true>), dim3(blocks), dim3(threads), lds, s, fin, pout, a, c,
+                         kx2, kz2, blist, ya);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_ysolve<T, M, MODE, DROP, false>), dim3(blocks), dim3(threads), lds, s, fin, pout, a, c, kx2,
+                     kz2, blist, ya);
   return hipGetLastError();
 }
 
