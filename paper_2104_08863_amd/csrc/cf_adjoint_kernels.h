@@ -209,7 +209,9 @@ struct AdjPtrs {
 // (xcd_slab_block; one run over the whole grid is as fast in FP32 and 12 %
 // slower in FP64): the two launches of one adjoint step take 70.8 ms instead
 // of 82.8 on 2048x768x2048 in FP32, 5.7 instead of 6.5 on 1024x256x512 in FP64.
-template <typename T, int TX, int TZ, int CY, bool HASB, bool ADD>
+// NT: outputs, written once, stored non-temporally for large fields (the
+// two launches of an FP32 adjoint step on 2048x768x2048: 72-74 -> 71.5 ms).
+template <typename T, int TX, int TZ, int CY, bool HASB, bool ADD, bool NT>
 __global__ void __launch_bounds__(TX * TZ)
 k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
   constexpr int SX = TX + 2, SZ = TZ + 2, PLANE = SX * SZ, TH = TX * TZ;
@@ -331,9 +333,9 @@ k_rhs_adjoint(AdjPtrs P, T c1, T c2, AdjGeo<T> G, T nu, T s) {
     }
     if (mine) {
       const long id = (long)j * plane + pid;
-      gu[id] = ou;
-      gv[id] = (j == ny - 1) ? T(0) : ov;
-      gw[id] = ow;
+      st_once<NT>(ou, &gu[id]);
+      st_once<NT>((j == ny - 1) ? T(0) : ov, &gv[id]);
+      st_once<NT>(ow, &gw[id]);
     }
     __syncthreads();
   }

@@ -29,14 +29,24 @@ hipError_t launch_rhs_adjoint(const T* u, const T* v, const T* w, const T* au, c
   const long blocks = (long)((g.g.nx + ADJ_TX - 1) / ADJ_TX) * ((g.g.nz + ADJ_TZ - 1) / ADJ_TZ) *
                       ((g.g.ny + ADJ_CY - 1) / ADJ_CY);
   const dim3 grid(blocks), block(ADJ_TX * ADJ_TZ);
-  if (bu != nullptr && add)
-    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, true, true>), grid, block, 0, st, P, c1, c2, g, nu, s);
-  else if (bu != nullptr)
-    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, true, false>), grid, block, 0, st, P, c1, c2, g, nu, s);
-  else if (add)
-    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, false, true>), grid, block, 0, st, P, c1, c2, g, nu, s);
-  else
-    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, false, false>), grid, block, 0, st, P, c1, c2, g, nu, s);
+  const bool nt = (long)g.g.nx * g.g.ny * g.g.nz * (long)sizeof(T) >= kStreamBytes;
+#define CF_ADJ_GO(HASB, ADD)                                                                                     \
+  if (nt)                                                                                                        \
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, HASB, ADD, true>), grid, block, 0, st, P, c1, c2, \
+                       g, nu, s);                                                                                \
+  else                                                                                                           \
+    hipLaunchKernelGGL((k_rhs_adjoint<T, ADJ_TX, ADJ_TZ, ADJ_CY, HASB, ADD, false>), grid, block, 0, st, P, c1,   \
+                       c2, g, nu, s)
+  if (bu != nullptr && add) {
+    CF_ADJ_GO(true, true);
+  } else if (bu != nullptr) {
+    CF_ADJ_GO(true, false);
+  } else if (add) {
+    CF_ADJ_GO(false, true);
+  } else {
+    CF_ADJ_GO(false, false);
+  }
+#undef CF_ADJ_GO
   return hipGetLastError();
 }
 

@@ -16,12 +16,18 @@ hipError_t launch_rk_stage(int stage, const T* u, const T* v, const T* w, const 
   const long blocks = (long)((g.nx + RK_TX - 1) / RK_TX) * ((g.nz + RK_TZ - 1) / RK_TZ) *
                       ((g.ny + RK_CY - 1) / RK_CY);
   const dim3 th(RK_TX * RK_TZ);
-  if (stage == 1)
-    hipLaunchKernelGGL((k_rk_stage<T, 1, RK_TX, RK_TZ, RK_CY>), dim3(blocks), th, 0, s, u, v, w, u0, v0, w0,
-                       uo, vo, wo, g, dt, nu, fx);
-  else
-    hipLaunchKernelGGL((k_rk_stage<T, 2, RK_TX, RK_TZ, RK_CY>), dim3(blocks), th, 0, s, u, v, w, u0, v0, w0,
-                       uo, vo, wo, g, dt, nu, fx);
+  const bool nt = (long)g.nx * g.ny * g.nz * (long)sizeof(T) >= kStreamBytes;
+#define CF_RK_GO(ST, NT)                                                                                         \
+  hipLaunchKernelGGL((k_rk_stage<T, ST, RK_TX, RK_TZ, RK_CY, NT>), dim3(blocks), th, 0, s, u, v, w, u0, v0, w0, \
+                     uo, vo, wo, g, dt, nu, fx)
+  if (stage == 1) {
+    if (nt) CF_RK_GO(1, true);
+    else CF_RK_GO(1, false);
+  } else {
+    if (nt) CF_RK_GO(2, true);
+    else CF_RK_GO(2, false);
+  }
+#undef CF_RK_GO
   return hipGetLastError();
 }
 
